@@ -1,0 +1,186 @@
+"""Benchmark: unknowns solved per second for a series of symmetric
+tridiagonal systems on one MI355X, FP32-refined path vs plain FP64 path.
+
+Workload: 1-D Poisson series, M = 4096 rows, N = 4096 right-hand sides
+(each a sum of 8 random sine modes plus U[-1e-3, 1e-3] noise, stored as
+FP32), P = 64 blocks of 64 rows, RHS-interleaved layout.  One step = one
+full solve of the series (beta weights, interface step, block sweeps) from
+inputs already resident in device memory.  Several input/output buffer
+sets are rotated so that consecutive steps do not find their data in the
+256 MB last-level cache.
+
+Prints one JSON line (see the keys below).  --gpus above 1 is refused: the
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--mode", default="f32_refined",
+                   choices=["f32_refined", "f64", "f32_wide", "f32"])
+    p.add_argument("--M", type=int, default=4096)
+    p.add_argument("--N", type=int, default=4096)
+    p.add_argument("--P", type=int, default=64)
+    p.add_argument("--sets", type=int, default=0,
+                   help="buffer sets rotated across steps (0: enough to exceed 512 MB)")
+    p.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison runs")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    return p.parse_args()
+
+
+def time_mode(plan, F_sets, X_sets, mode, steps, warmup, torch):
+    n_sets = len(F_sets)
+    for k in range(warmup):
+        plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    plan.timing_read()                 # clear
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for k in range(steps):
+        plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    ms_beta, ms_iface, ms_sweep, calls = plan.timing_read()
+    plan.timing(False)
+    return dict(ms_per_step=ms_total / steps, wall_s=wall,
+                ms_beta=ms_beta / calls, ms_iface=ms_iface / calls,
+                ms_sweep=ms_sweep / calls)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0901_2859_amd import tdsolve as t
+    from paper_0901_2859_amd import workloads as wl
+
+    M, N, P = args.M, args.N, args.P
+    w = wl.poisson_series(M=M, N=N, P=P)
+    a, b, F32 = w["a"], w["b"], w["F"]
+    dev = torch.device("cuda:0")
+    plan = t.Plan(a, b, P)
+
+    f_bytes = {"f32_refined": 4, "f32_wide": 4, "f32": 4, "f64": 8}
+    x_bytes = {"f32_refined": 8, "f32_wide": 8, "f32": 4, "f64": 8}
+
+    def make_sets(mode):
+        per_set = M * N * (f_bytes[mode] + x_bytes[mode])
+        n_sets = args.sets or max(1, -(-(512 << 20) // per_set) + 1)
+        Fd = torch.from_numpy(F32).to(dev)
+        if f_bytes[mode] == 8:
+            Fd = Fd.double()
+        xdt = torch.float64 if x_bytes[mode] == 8 else torch.float32
+        Fs = [Fd] + [Fd.clone() for _ in range(n_sets - 1)]
+        Xs = [torch.empty((M, N), dtype=xdt, device=dev) for _ in range(n_sets)]
+        return Fs, Xs
+
+    def run(mode, steps, warmup):
+        Fs, Xs = make_sets(mode)
+        r = time_mode(plan, Fs, Xs, mode, steps, warmup, torch)
+        eta, r2 = plan.residual(Fs[0], Xs[0], mode=mode)
+        torch.cuda.synchronize()
+        r["eta_max"] = float(eta.max())
+        r["r2_max"] = float(r2.max())
+        r["sets"] = len(Fs)
+        r["unknowns_per_s"] = M * N / (r["ms_per_step"] * 1e-3)
+        alg = M * N * (f_bytes[mode] + x_bytes[mode])
+        r["path_gbs"] = alg / (r["ms_per_step"] * 1e-3) / 1e9
+        del Fs, Xs
+        torch.cuda.empty_cache()
+        return r
+
+    main_r = run(args.mode, args.steps, args.warmup)
+
+    # dominant kernel: the block sweep (reads F, writes X, reads two
+    # interface values per block and right-hand side)
+    sweep_bytes = M * N * (f_bytes[args.mode] + x_bytes[args.mode]) + 2 * (P - 1) * N * 8
+    ms_sweep = main_r["ms_sweep"]
+    achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep_reg", "bytes_per_launch": sweep_bytes,
+                "ms_per_launch": round(ms_sweep, 5)}
+
+    compare = {}
+    if not args.no_compare:
+        for mode in ("f64", "f32_wide"):
+            if mode == args.mode:
+                continue
+            r = run(mode, max(10, args.steps // 2), max(3, args.warmup // 2))
+            compare[mode] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        Fw = F32.astype(np.float64)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.thomas(a, b, Fw)
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": reps * M * N / el, "unit": "unknowns/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"FP64 sequential sweep per RHS (OpenMP over RHS) on the full "
+                         f"{M}x{N} Poisson series, repeated {reps}x over {el:.1f} s"}
+
+    out = {
+        "metric": "unknowns solved/s + % HBM peak, FP32-refined vs FP64 plain at equal residual",
+        "value": main_r["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32_refined": "f32+f64", "f64": "f64", "f32_wide": "f32->f64", "f32": "f32"}[args.mode],
+        "data": "synthetic",
+        "config": {"workload": "1-D Poisson series (sum of 8 sine modes + noise), FP32 storage "
+                               "with FP64 refinement", "M": M, "N": N, "P": P,
+                   "mode": args.mode, "layout": "RHS-interleaved [M][N]",
+                   "buffer_sets": main_r["sets"]},
+        "hbm_frac_path": round(main_r["path_gbs"] / HBM_PEAK_GBS, 4),
+        "path_gbs": round(main_r["path_gbs"], 1),
+        "phases_ms": {"beta": round(main_r["ms_beta"], 5), "interface": round(main_r["ms_iface"], 5),
+                      "sweep": round(main_r["ms_sweep"], 5)},
+        "r2_max": main_r["r2_max"],
+        "eta_max": main_r["eta_max"],
+        "roofline": roofline,
+        "compare": compare,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

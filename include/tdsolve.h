@@ -1,0 +1,186 @@
+/*
+ * tdsolve -- series of symmetric tridiagonal systems on AMD Instinct MI355X
+ * (gfx950), by the parallel sweep method of A.V. Terekhov, "Parallel
+ * dichotomy algorithm for solving tridiagonal SLAEs" (arXiv:0901.2859).
+ *
+ * Problem (section 2, "Statement of the problem", eq. main_eq3):
+ *     A X_n = F_n,  n = 1..N,
+ * with one constant, symmetric, nondegenerate tridiagonal M x M matrix A:
+ * diagonal b[0..M-1], off-diagonal a[0..M-2], A[i][i+1] = A[i+1][i] = a[i].
+ *
+ * Method (section 3):
+ *  - data decomposition (section 2): rows split into P contiguous blocks of
+ *    at least 2 rows; the first M mod P blocks get one extra row;
+ *  - preliminary step, once per matrix, in FP64 (Algorithm 3 step 1;
+ *    Lemma 2, eq. green_v; eq. z_vector; Remark 1): the rows of A^{-1} at
+ *    the P-1 interface rows (the first row of blocks 1..P-1) and the
+ *    transfer factors of the vectors Z^R, Z^L between neighbouring
+ *    interface rows;
+ *  - per right-hand side (Algorithm 3 step 2): the weights beta^{R,L} of
+ *    every block (eq. beta_symn), the interface components by the main
+ *    parallel sweep theorem (Theorem 2, eq. theor_2, evaluated as two
+ *    first-order recurrences over the blocks), then independent sweeps
+ *    inside every block with its boundary values known (Lemma 1,
+ *    Algorithm 1).
+ *
+ * Layout.  Every N-column array is RHS-interleaved, row-major [M][N]:
+ * element (row i, right-hand side n) is at offset i*N + n.
+ *
+ * Precision modes (TDS_*):
+ *   TDS_F64          F double, X double; FP64 sweeps.
+ *   TDS_F32_REFINED  F float,  X double; FP32 sweeps inside each block with
+ *                    FP64 interface values and FP64 residual-based
+ *                    refinement passes, all in registers (default 2 passes).
+ *   TDS_F32          F float,  X float;  FP32 sweeps, FP64 interface step.
+ *   TDS_F32_WIDE     F float,  X double; FP64 sweeps of the widened input.
+ *
+ * Memory.  a, b are host arrays owned by the caller, copied by prepare.
+ * F, X, gX, gF, ga, gb, and the output buffers of tdsolve_components and
+ * tdsolve_residual are device pointers (the current HIP device) owned by
+ * the caller.  X may equal F only when both have the same element type;
+ * any other overlap is undefined.  A handle owns its device tables and a
+ * work buffer that grows with N; calls on one handle must be ordered on a
+ * single stream (use one handle per concurrent stream).
+ *
+ * Errors.  Every entry point returns a tds_status code; no exception crosses
+ * the ABI.  Launches are asynchronous on `stream` (a hipStream_t, NULL =
+ * the default stream); a launch failure returns TDS_EHIP.
+ */
+#ifndef TDSOLVE_H
+#define TDSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tds_plan* tds_handle;
+
+typedef enum {
+    TDS_OK = 0,
+    TDS_EINVAL = -1,        /* bad argument: sizes, null pointer, NaN/Inf in a or b */
+    TDS_ESINGULAR = -2,     /* zero or non-finite pivot in the FP64 preliminary step */
+    TDS_ENOMEM = -3,        /* host or device allocation failed */
+    TDS_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
+    TDS_ENOCONV = -5,       /* reserved: refinement did not converge */
+    TDS_EUNSUPPORTED = -6   /* valid request this build does not handle */
+} tds_status;
+
+typedef enum {
+    TDS_F64 = 0,
+    TDS_F32_REFINED = 1,
+    TDS_F32 = 2,
+    TDS_F32_WIDE = 3
+} tds_mode;
+
+/* Facts about a prepared matrix (host struct filled by tdsolve_info). */
+typedef struct {
+    int64_t M;            /* rows */
+    int32_t P;            /* blocks */
+    int32_t max_block;    /* largest block size t_j */
+    int32_t dominant;     /* 1 if |b_i| >= |a_{i-1}| + |a_i| with one strict
+                             inequality (Theorem 4's stability condition) */
+    int32_t refine_passes;/* passes used by TDS_F32_REFINED */
+    double max_ratio;     /* max |Z_{k+1}/Z_k| over both sweeps; <= 1 under
+                             dominance (proof of Theorem 4) */
+} tds_info;
+
+/* Preliminary step (Algorithm 3 step 1).  a: M-1 host doubles (may be NULL
+ * when M == 1), b: M host doubles.  P: number of blocks, 1 <= P <= M/2
+ * (P == 1 allowed for any M >= 1); P == 0 picks a block count from the
+ * library's size table.  On success *out receives a new handle.
+ * Errors: TDS_EINVAL (sizes, NULL, non-finite a or b), TDS_ESINGULAR (an
+ * elimination or ratio denominator is zero or non-finite in FP64),
+ * TDS_ENOMEM, TDS_EHIP (device upload). */
+int tdsolve_prepare(const double* a, const double* b, int64_t M, int32_t P,
+                    tds_handle* out);
+
+/* Solve the series (Algorithm 1 with Algorithm 3 step 2 for the interface
+ * rows).  F: device [M][N] (double for TDS_F64, float otherwise).
+ * X: device [M][N] (float for TDS_F32, double otherwise).  N >= 0 (N == 0
+ * is a no-op).  Asynchronous on `stream`. */
+int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N,
+                   int32_t mode, void* stream);
+
+/* Algorithm 3 alone: the solution components at the P-1 interface rows for
+ * every right-hand side, without the block sweeps.  Xsep: device double
+ * [P-1][N]; row k-1 holds x at the first row of block k.  F as for
+ * tdsolve_series (mode selects the element type of F only). */
+int tdsolve_components(tds_handle h, const void* F, double* Xsep, int64_t N,
+                       int32_t mode, void* stream);
+
+/* Adjoint of X = A^{-1} F for a loss L with dL/dX = gX (device [M][N],
+ * same element type as X of `mode`).  Since A is symmetric (Lemma 2), the
+ * same prepared plan gives gF = A^{-1} gX (written to gF, same element type
+ * as F of `mode`).  ga (M-1 doubles) and gb (M doubles), device pointers,
+ * are overwritten with dL/da and dL/db:
+ *   gb_i = -sum_n gF[i][n] X[i][n],
+ *   ga_i = -sum_n (gF[i][n] X[i+1][n] + gF[i+1][n] X[i][n]).
+ * Either may be NULL to skip it.  X: device [M][N] forward solution (same
+ * element type as gX).  Reductions are in a fixed order (bitwise
+ * reproducible). */
+int tdsolve_backward(tds_handle h, const void* X, const void* gX, void* gF,
+                     double* ga, double* gb, int64_t N, int32_t mode,
+                     void* stream);
+
+/* Residual check of a computed solution: for every right-hand side n,
+ * out[n] = ||F_n - A X_n||_inf / (||A||_inf ||X_n||_inf + ||F_n||_inf)
+ * (normwise backward error) and out[N + n] = ||F_n - A X_n||_2 / ||F_n||_2.
+ * F, X as for tdsolve_series with `mode`; out: device double [2N]. */
+int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N,
+                     int32_t mode, double* out, void* stream);
+
+/* Per-phase timing for measurement.  While enabled, every tdsolve_series
+ * call on the handle records HIP events on its stream around its three
+ * kernel phases.  tdsolve_timing_read waits for the last recorded event,
+ * writes the accumulated milliseconds of [0] the beta weights, [1] the
+ * interface step and [2] the block sweeps into ms (3 host doubles) and the
+ * number of timed calls into *calls, then clears the record. */
+int tdsolve_timing_enable(tds_handle h, int32_t on);
+int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
+
+/* Number of refinement passes for TDS_F32_REFINED (0..8; default 2). */
+int tdsolve_set_refinement(tds_handle h, int32_t passes);
+
+int tdsolve_info(tds_handle h, tds_info* info);
+
+/* Host-only copy of the preliminary step's FP64 tables, for checks without
+ * a GPU.  Any output pointer may be NULL.  Sizes: starts P+1 (int64),
+ * wR, wL: M (row i of segment j holds (A^{-1})[s_{j+1}][i] in wR and
+ * (A^{-1})[s_j][i] in wL, 0 where undefined), rho, lam: P (rho[k], lam[k]
+ * for k = 1..P-2 link interface rows k and k+1; other entries 0),
+ * diag_inv: M (the diagonal of A^{-1}).  Same errors as prepare except
+ * TDS_EHIP / device errors, which cannot occur. */
+int tdsolve_prepare_host(const double* a, const double* b, int64_t M,
+                         int32_t P, int64_t* starts, double* wR, double* wL,
+                         double* rho, double* lam, double* diag_inv);
+
+/* Block count the library would choose for P == 0. */
+int32_t tdsolve_default_blocks(int64_t M);
+
+int tdsolve_destroy(tds_handle h);
+
+const char* tdsolve_strerror(int code);
+
+/* ---- uneven batches: K independent matrices in one launch sequence ----
+ * Each matrix k has its own a[k] (M[k]-1 doubles), b[k] (M[k] doubles),
+ * block count P[k] (0 = library choice) and series of N[k] right-hand
+ * sides.  The batch handle owns the concatenated tables of all K plans. */
+int tdsolve_batch_prepare(int32_t K, const double* const* a,
+                          const double* const* b, const int64_t* M,
+                          const int32_t* P, tds_handle* out);
+
+/* F[k], X[k]: device pointers of matrix k's [M[k]][N[k]] arrays (element
+ * types by `mode` as for tdsolve_series); the pointer arrays themselves are
+ * host arrays of K entries.  N: host array of K counts (0 allowed).  All K
+ * series are solved by one launch of each kernel. */
+int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
+                         const int64_t* N, int32_t mode, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDSOLVE_H */

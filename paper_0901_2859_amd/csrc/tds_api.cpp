@@ -1,0 +1,377 @@
+// C ABI of the tdsolve library (declared in include/tdsolve.h): argument
+// checks, device tables of the preliminary step, work buffers and the
+// launch sequence of the per-right-hand-side step.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "tdsolve.h"
+#include "tds_internal.h"
+
+using namespace tds;
+
+struct tds_plan {
+    HostTables host;
+    DevTables dev;
+    void* dev_mem = nullptr;
+    double normA = 0.0;          // ||A||_inf
+    int32_t passes = 2;          // refinement passes of TDS_F32_REFINED
+    int device = 0;
+    void* work = nullptr;        // grows with N
+    size_t work_bytes = 0;
+    bool timing = false;         // record per-phase events
+    std::vector<hipEvent_t> events;  // 4 per timed call
+    size_t events_used = 0;
+};
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int upload(tds_plan* h) {
+    const HostTables& o = h->host;
+    const int64_t M = o.M;
+    const int32_t P = o.P;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+    const size_t o_starts = take(sizeof(int64_t) * (P + 1));
+    const size_t o_wR = take(sizeof(double) * M), o_wL = take(sizeof(double) * M);
+    const size_t o_rho = take(sizeof(double) * P), o_lam = take(sizeof(double) * P);
+    const size_t o_a64 = take(sizeof(double) * M), o_b64 = take(sizeof(double) * M);
+    const size_t o_cp64 = take(sizeof(double) * M), o_rd64 = take(sizeof(double) * M);
+    const size_t o_a32 = take(sizeof(float) * M), o_cp32 = take(sizeof(float) * M);
+    const size_t o_rd32 = take(sizeof(float) * M);
+    const size_t total = off;
+
+    std::vector<unsigned char> img(total, 0);
+    auto put = [&](size_t at, const void* src, size_t bytes) { memcpy(img.data() + at, src, bytes); };
+    put(o_starts, o.starts.data(), sizeof(int64_t) * (P + 1));
+    put(o_wR, o.wR.data(), sizeof(double) * M);
+    put(o_wL, o.wL.data(), sizeof(double) * M);
+    put(o_rho, o.rho.data(), sizeof(double) * P);
+    put(o_lam, o.lam.data(), sizeof(double) * P);
+    put(o_a64, o.a64.data(), sizeof(double) * M);
+    put(o_b64, o.b64.data(), sizeof(double) * M);
+    put(o_cp64, o.cp64.data(), sizeof(double) * M);
+    put(o_rd64, o.rd64.data(), sizeof(double) * M);
+    std::vector<float> f(M);
+    for (int64_t i = 0; i < M; ++i) f[i] = (float)o.a64[i];
+    put(o_a32, f.data(), sizeof(float) * M);
+    for (int64_t i = 0; i < M; ++i) f[i] = (float)o.cp64[i];
+    put(o_cp32, f.data(), sizeof(float) * M);
+    for (int64_t i = 0; i < M; ++i) f[i] = (float)o.rd64[i];
+    put(o_rd32, f.data(), sizeof(float) * M);
+
+    if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, total);
+    if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
+    if (e != hipSuccess) return TDS_EHIP;
+    if (hipMemcpy(mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        return TDS_EHIP;
+    }
+    h->dev_mem = mem;
+    unsigned char* base = (unsigned char*)mem;
+    DevTables& d = h->dev;
+    d.M = M;
+    d.P = P;
+    d.max_rows = o.max_rows;
+    d.starts = (int64_t*)(base + o_starts);
+    d.wR = (double*)(base + o_wR);
+    d.wL = (double*)(base + o_wL);
+    d.rho = (double*)(base + o_rho);
+    d.lam = (double*)(base + o_lam);
+    d.a64 = (double*)(base + o_a64);
+    d.b64 = (double*)(base + o_b64);
+    d.cp64 = (double*)(base + o_cp64);
+    d.rd64 = (double*)(base + o_rd64);
+    d.a32 = (float*)(base + o_a32);
+    d.cp32 = (float*)(base + o_cp32);
+    d.rd32 = (float*)(base + o_rd32);
+    return TDS_OK;
+}
+
+int ensure_work(tds_plan* h, size_t bytes) {
+    if (bytes <= h->work_bytes) return TDS_OK;
+    if (h->work) {
+        // the previous buffer may still be in use by queued work
+        if (hipDeviceSynchronize() != hipSuccess) return TDS_EHIP;
+        (void)hipFree(h->work);
+        h->work = nullptr;
+        h->work_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->work, bytes);
+    if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
+    if (e != hipSuccess) return TDS_EHIP;
+    h->work_bytes = bytes;
+    return TDS_OK;
+}
+
+bool valid_mode(int32_t m) { return m >= TDS_F64 && m <= TDS_F32_WIDE; }
+size_t f_elem(int32_t m) { return m == TDS_F64 ? 8 : 4; }
+size_t x_elem(int32_t m) { return m == TDS_F32 ? 4 : 8; }
+
+int check_common(tds_plan* h, int64_t N, int32_t mode) {
+    if (!h) return TDS_EINVAL;
+    if (N < 0 || !valid_mode(mode)) return TDS_EINVAL;
+    if ((N + kWG - 1) / kWG > 0x7fffffffLL) return TDS_EUNSUPPORTED;
+    return TDS_OK;
+}
+
+// beta + interface step into xsep; work layout: betaR | betaL | xsep(optional)
+int interface_step(tds_plan* h, const void* F, int64_t N, int32_t mode, double* xsep,
+                   double* betaR, double* betaL, hipStream_t s) {
+    const DevTables& t = h->dev;
+    if (t.P < 2) return TDS_OK;
+    if (launch_beta(t, F, mode != TDS_F64, N, betaR, betaL, s) != hipSuccess) return TDS_EHIP;
+    if (launch_iface(t, betaR, betaL, xsep, N, s) != hipSuccess) return TDS_EHIP;
+    return TDS_OK;
+}
+
+hipEvent_t* timing_slot(tds_plan* h) {
+    if (!h->timing) return nullptr;
+    while (h->events.size() < h->events_used + 4) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->events.push_back(e);
+    }
+    hipEvent_t* ev = h->events.data() + h->events_used;
+    h->events_used += 4;
+    return ev;
+}
+
+int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hipStream_t s,
+                int sweep_mode) {
+    const DevTables& t = h->dev;
+    const int64_t P = t.P;
+    const size_t nb = sizeof(double) * (size_t)P * (size_t)N;
+    int rc = ensure_work(h, align256(nb) * 2 + align256(sizeof(double) * (size_t)(P > 1 ? P - 1 : 1) * N));
+    if (rc) return rc;
+    double* betaR = (double*)h->work;
+    double* betaL = (double*)((char*)h->work + align256(nb));
+    double* xsep = (double*)((char*)h->work + 2 * align256(nb));
+    hipEvent_t* ev = timing_slot(h);
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TDS_EHIP;
+    if (t.P >= 2) {
+        if (launch_beta(t, F, mode != TDS_F64, N, betaR, betaL, s) != hipSuccess) return TDS_EHIP;
+        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TDS_EHIP;
+        if (launch_iface(t, betaR, betaL, xsep, N, s) != hipSuccess) return TDS_EHIP;
+    } else if (ev && hipEventRecord(ev[1], s) != hipSuccess) {
+        return TDS_EHIP;
+    }
+    if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TDS_EHIP;
+    if (launch_sweep(t, F, X, N, sweep_mode, h->passes, xsep, s) != hipSuccess) return TDS_EHIP;
+    if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TDS_EHIP;
+    return TDS_OK;
+}
+
+__global__ void k_cast_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride) dst[k] = (float)src[k];
+}
+
+}  // namespace
+
+extern "C" {
+
+int tdsolve_prepare(const double* a, const double* b, int64_t M, int32_t P, tds_handle* out) {
+    if (!out) return TDS_EINVAL;
+    *out = nullptr;
+    tds_plan* h = new (std::nothrow) tds_plan();
+    if (!h) return TDS_ENOMEM;
+    int rc = host_prepare(a, b, M, P, h->host);
+    if (rc) { delete h; return rc; }
+    if (h->host.P > 65535) { delete h; return TDS_EUNSUPPORTED; }
+    double normA = 0.0;
+    for (int64_t i = 0; i < M; ++i) {
+        double r = fabs(h->host.b64[i]) + (i > 0 ? fabs(h->host.a64[i - 1]) : 0.0) +
+                   fabs(h->host.a64[i]);
+        normA = std::max(normA, r);
+    }
+    h->normA = normA;
+    rc = upload(h);
+    if (rc) { delete h; return rc; }
+    *out = h;
+    return TDS_OK;
+}
+
+int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N, int32_t mode, void* stream) {
+    int rc = check_common(h, N, mode);
+    if (rc) return rc;
+    if (N == 0) return TDS_OK;
+    if (!F || !X) return TDS_EINVAL;
+    if (F == X && f_elem(mode) != x_elem(mode)) return TDS_EINVAL;
+    return series_impl(h, F, X, N, mode, (hipStream_t)stream, mode);
+}
+
+int tdsolve_components(tds_handle h, const void* F, double* Xsep, int64_t N, int32_t mode,
+                       void* stream) {
+    int rc = check_common(h, N, mode);
+    if (rc) return rc;
+    if (N == 0 || h->dev.P < 2) return TDS_OK;
+    if (!F || !Xsep) return TDS_EINVAL;
+    const size_t nb = sizeof(double) * (size_t)h->dev.P * (size_t)N;
+    rc = ensure_work(h, align256(nb) * 2);
+    if (rc) return rc;
+    double* betaR = (double*)h->work;
+    double* betaL = (double*)((char*)h->work + align256(nb));
+    return interface_step(h, F, N, mode, Xsep, betaR, betaL, (hipStream_t)stream);
+}
+
+int tdsolve_backward(tds_handle h, const void* X, const void* gX, void* gF, double* ga,
+                     double* gb, int64_t N, int32_t mode, void* stream) {
+    int rc = check_common(h, N, mode);
+    if (rc) return rc;
+    if (N == 0) {
+        hipStream_t s = (hipStream_t)stream;
+        if (ga && h->dev.M > 1 && hipMemsetAsync(ga, 0, sizeof(double) * (h->dev.M - 1), s) != hipSuccess) return TDS_EHIP;
+        if (gb && hipMemsetAsync(gb, 0, sizeof(double) * h->dev.M, s) != hipSuccess) return TDS_EHIP;
+        return TDS_OK;
+    }
+    if (!X || !gX || !gF) return TDS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const DevTables& t = h->dev;
+    if (mode == TDS_F64 || mode == TDS_F32) {
+        // gX and gF have the same element type: solve straight into gF
+        rc = series_impl(h, gX, gF, N, mode, s, mode);
+        if (rc) return rc;
+        const bool f32 = (mode == TDS_F32);
+        if (launch_adjoint_reduce(t, X, gF, f32, f32, N, nullptr, ga, gb, s) != hipSuccess)
+            return TDS_EHIP;
+        return TDS_OK;
+    }
+    // X, gX are double, F (hence gF) is float: solve in FP64 into a private
+    // FP64 buffer, reduce from it, then round into gF.
+    const size_t gbytes = align256(sizeof(double) * (size_t)t.M * (size_t)N);
+    void* g64 = nullptr;
+    hipError_t e = hipMallocAsync(&g64, gbytes, s);
+    if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
+    if (e != hipSuccess) return TDS_EHIP;
+    rc = series_impl(h, gX, g64, N, TDS_F64, s, TDS_F64);
+    if (!rc && launch_adjoint_reduce(t, X, g64, false, false, N, nullptr, ga, gb, s) != hipSuccess)
+        rc = TDS_EHIP;
+    if (!rc) {
+        const int64_t n = t.M * N;
+        unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_cast_f32, dim3(blocks), dim3(256), 0, s, (const double*)g64,
+                           (float*)gF, n);
+        if (hipGetLastError() != hipSuccess) rc = TDS_EHIP;
+    }
+    if (hipFreeAsync(g64, s) != hipSuccess && !rc) rc = TDS_EHIP;
+    return rc;
+}
+
+int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N, int32_t mode,
+                     double* out, void* stream) {
+    int rc = check_common(h, N, mode);
+    if (rc) return rc;
+    if (N == 0) return TDS_OK;
+    if (!F || !X || !out) return TDS_EINVAL;
+    const int64_t chunks = (h->dev.M + kReduceRowChunk - 1) / kReduceRowChunk;
+    if (chunks > 65535) return TDS_EUNSUPPORTED;
+    rc = ensure_work(h, sizeof(double) * 5 * (size_t)chunks * (size_t)N);
+    if (rc) return rc;
+    if (launch_residual(h->dev, F, X, N, mode, h->normA, (double*)h->work, out,
+                        (hipStream_t)stream) != hipSuccess)
+        return TDS_EHIP;
+    return TDS_OK;
+}
+
+int tdsolve_timing_enable(tds_handle h, int32_t on) {
+    if (!h) return TDS_EINVAL;
+    h->timing = (on != 0);
+    return TDS_OK;
+}
+
+int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls) {
+    if (!h || !ms) return TDS_EINVAL;
+    ms[0] = ms[1] = ms[2] = 0.0;
+    const size_t ncalls = h->events_used / 4;
+    if (ncalls > 0 && hipEventSynchronize(h->events[h->events_used - 1]) != hipSuccess)
+        return TDS_EHIP;
+    for (size_t c = 0; c < ncalls; ++c) {
+        hipEvent_t* e = h->events.data() + 4 * c;
+        for (int k = 0; k < 3; ++k) {
+            float v = 0.0f;
+            if (hipEventElapsedTime(&v, e[k], e[k + 1]) != hipSuccess) return TDS_EHIP;
+            ms[k] += v;
+        }
+    }
+    if (calls) *calls = (int64_t)ncalls;
+    h->events_used = 0;
+    return TDS_OK;
+}
+
+int tdsolve_set_refinement(tds_handle h, int32_t passes) {
+    if (!h || passes < 0 || passes > 8) return TDS_EINVAL;
+    h->passes = passes;
+    return TDS_OK;
+}
+
+int tdsolve_info(tds_handle h, tds_info* info) {
+    if (!h || !info) return TDS_EINVAL;
+    info->M = h->host.M;
+    info->P = h->host.P;
+    info->max_block = h->host.max_rows;
+    info->dominant = h->host.dominant;
+    info->refine_passes = h->passes;
+    info->max_ratio = h->host.max_ratio;
+    return TDS_OK;
+}
+
+int tdsolve_prepare_host(const double* a, const double* b, int64_t M, int32_t P, int64_t* starts,
+                         double* wR, double* wL, double* rho, double* lam, double* diag_inv) {
+    HostTables o;
+    int rc = host_prepare(a, b, M, P, o);
+    if (rc) return rc;
+    if (starts) memcpy(starts, o.starts.data(), sizeof(int64_t) * (o.P + 1));
+    if (wR) memcpy(wR, o.wR.data(), sizeof(double) * M);
+    if (wL) memcpy(wL, o.wL.data(), sizeof(double) * M);
+    if (rho) memcpy(rho, o.rho.data(), sizeof(double) * o.P);
+    if (lam) memcpy(lam, o.lam.data(), sizeof(double) * o.P);
+    if (diag_inv) memcpy(diag_inv, o.diag_inv.data(), sizeof(double) * M);
+    return TDS_OK;
+}
+
+int32_t tdsolve_default_blocks(int64_t M) { return default_blocks(M); }
+
+int tdsolve_destroy(tds_handle h) {
+    if (!h) return TDS_EINVAL;
+    if (h->work || h->dev_mem) (void)hipDeviceSynchronize();
+    if (h->work) (void)hipFree(h->work);
+    if (h->dev_mem) (void)hipFree(h->dev_mem);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    delete h;
+    return TDS_OK;
+}
+
+const char* tdsolve_strerror(int code) {
+    switch (code) {
+        case TDS_OK: return "ok";
+        case TDS_EINVAL: return "invalid argument";
+        case TDS_ESINGULAR: return "zero or non-finite pivot in the FP64 preliminary step";
+        case TDS_ENOMEM: return "out of memory";
+        case TDS_EHIP: return "HIP runtime or launch failure";
+        case TDS_ENOCONV: return "refinement did not converge";
+        case TDS_EUNSUPPORTED: return "unsupported size or mode";
+        default: return "unknown tdsolve status";
+    }
+}
+
+int tdsolve_batch_prepare(int32_t, const double* const*, const double* const*, const int64_t*,
+                          const int32_t*, tds_handle* out) {
+    if (out) *out = nullptr;
+    return TDS_EUNSUPPORTED;
+}
+
+int tdsolve_batch_series(tds_handle, const void* const*, void* const*, const int64_t*, int32_t,
+                         void*) {
+    return TDS_EUNSUPPORTED;
+}
+
+}  // extern "C"

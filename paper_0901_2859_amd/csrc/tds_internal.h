@@ -1,0 +1,76 @@
+// Internal declarations shared by the host side (prepare, C ABI) and the
+// HIP kernels of the tdsolve library.  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace tds {
+
+// Workgroup size of every per-block kernel: 4 wavefronts of 64 lanes, each
+// lane one right-hand side.
+constexpr int kWG = 256;
+
+// Largest block (rows of one segment) handled by the register-resident
+// sweep; larger blocks take the streaming sweep, which keeps the forward
+// elimination in the output array instead of registers.
+constexpr int kRegMaxRows = 128;
+
+// Device tables of one prepared matrix (all FP64 unless noted).  Row arrays
+// have M entries.  `starts` has P+1 entries (s_0 = 0 .. s_P = M).
+struct DevTables {
+    int64_t M = 0;
+    int32_t P = 0;
+    int32_t max_rows = 0;      // largest t_j
+    int64_t* starts = nullptr;
+    double* wR = nullptr;      // row of A^{-1} at the segment's right interface row
+    double* wL = nullptr;      // row of A^{-1} at the segment's left interface row
+    double* rho = nullptr;     // P: Z^R transfer factor from interface k to k+1
+    double* lam = nullptr;     // P: Z^L transfer factor from interface k+1 to k
+    double* a64 = nullptr;     // a[i] (0 at i = M-1)
+    double* b64 = nullptr;     // b[i]
+    double* cp64 = nullptr;    // block-restarted elimination: x_i + cp_i x_{i+1} = d_i
+    double* rd64 = nullptr;    // 1 / pivot
+    float* a32 = nullptr;
+    float* cp32 = nullptr;
+    float* rd32 = nullptr;
+};
+
+// Host-side FP64 preliminary step.  Returns a tds_status code.
+struct HostTables {
+    int64_t M = 0;
+    int32_t P = 0;
+    int32_t max_rows = 0;
+    int32_t dominant = 0;
+    double max_ratio = 0.0;
+    std::vector<int64_t> starts;
+    std::vector<double> wR, wL, rho, lam, diag_inv, a64, b64, cp64, rd64;
+};
+
+int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
+                 HostTables& out);
+int32_t default_blocks(int64_t M);
+
+// Kernel launchers (tdsolve_kernels.hip).  All return hipError_t.
+hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N,
+                       double* betaR, double* betaL, hipStream_t s);
+hipError_t launch_iface(const DevTables& t, const double* betaR,
+                        const double* betaL, double* xsep, int64_t N,
+                        hipStream_t s);
+hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
+                        int mode, int passes, const double* xsep,
+                        hipStream_t s);
+hipError_t launch_residual(const DevTables& t, const void* F, const void* X,
+                           int64_t N, int mode, double normA, double* part,
+                           double* out, hipStream_t s);
+hipError_t launch_adjoint_reduce(const DevTables& t, const void* X,
+                                 const void* gF, bool f32x, bool f32g,
+                                 int64_t N, double* part, double* ga,
+                                 double* gb, hipStream_t s);
+
+// Rows of partial sums used by the residual and adjoint reductions.
+constexpr int kReduceRowChunk = 64;
+
+}  // namespace tds

@@ -1,0 +1,178 @@
+// FP64 preliminary step of the parallel sweep method, on the host.
+//
+// Algorithm 3, step 1 asks for the rows G_k of A^{-1} at the interface rows
+// (Lemma 2, eq. green_v) and the vectors Z^R_k, Z^L_k (eq. z_vector).
+//
+// Rows G_k: as in the paper, each is the solution of A G_k = e_k by a sweep
+// (one shared forward factorization, then one elimination of e_k and one
+// back substitution per interface row, O(M) each); only the two segments
+// next to k are kept, since eq. beta_symn uses G_k on those alone.
+//
+// Vectors Z: homogeneous solutions normalised to 1 at k.  Their successive
+// ratios do not depend on k and follow two first-order recurrences:
+//   Z^L: l_i = z_{i-1} / z_i,  l_1 = -a_0 / b_0,
+//        l_{i+1} = -a_i / (b_i + a_{i-1} l_i);
+//   Z^R: r_i = z_{i+1} / z_i,  r_{M-2} = -a_{M-2} / b_{M-1},
+//        r_{i-1} = -a_{i-1} / (b_i + a_i r_i),
+// so Z^L_k(i) = prod_{m=i+1..k} l_m and Z^R_k(i) = prod_{m=k..i-1} r_m
+// (these are the sweep coefficients alpha of the proof of Theorem 4;
+// |l|, |r| <= 1 under diagonal dominance).  Theorem 2 only needs Z between
+// neighbouring interface rows s_k < s_{k+1}:
+//   rho_k = Z^R_{s_k}(s_{k+1}),  lam_k = Z^L_{s_{k+1}}(s_k).
+// The diagonal of A^{-1} reported for checks is 1 / (b_k + a_{k-1} l_k +
+// a_k r_k) away from the interface rows.
+// The block sweeps (Lemma 1) use the elimination factors of each block's
+// interior rows, restarted at the first interior row of every block.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "tdsolve.h"
+#include "tds_internal.h"
+
+namespace tds {
+
+static bool bad(double v) { return !(v == v) || isinf(v); }
+
+int32_t default_blocks(int64_t M) {
+    // 64 rows per block keeps the register-resident sweep at its best size;
+    // short systems use as many blocks of at least 2 rows as fit.
+    if (M < 4) return 1;
+    int64_t P = (M + 63) / 64;
+    P = std::max<int64_t>(1, std::min<int64_t>(P, M / 2));
+    return (int32_t)std::min<int64_t>(P, 1 << 20);
+}
+
+int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
+                 HostTables& o) {
+    if (M < 1 || b == nullptr || (M > 1 && a == nullptr)) return TDS_EINVAL;
+    if (M > (int64_t(1) << 40)) return TDS_EINVAL;
+    if (P == 0) P = default_blocks(M);
+    if (P < 1) return TDS_EINVAL;
+    if (P > 1 && (int64_t)P * 2 > M) return TDS_EINVAL;
+    for (int64_t i = 0; i < M; ++i)
+        if (bad(b[i])) return TDS_EINVAL;
+    for (int64_t i = 0; i + 1 < M; ++i)
+        if (bad(a[i])) return TDS_EINVAL;
+
+    o.M = M;
+    o.P = P;
+    o.starts.assign(P + 1, 0);
+    const int64_t base = M / P, extra = M % P;
+    o.max_rows = 0;
+    for (int32_t j = 0; j < P; ++j) {
+        int64_t tj = base + (j < extra ? 1 : 0);
+        o.starts[j + 1] = o.starts[j] + tj;
+        o.max_rows = (int32_t)std::max<int64_t>(o.max_rows, tj);
+    }
+
+    o.a64.assign(M, 0.0);
+    o.b64.assign(b, b + M);
+    for (int64_t i = 0; i + 1 < M; ++i) o.a64[i] = a[i];
+    const double* A = o.a64.data();
+
+    // ratio recurrences
+    std::vector<double> l(M, 0.0), r(M, 0.0);
+    double max_ratio = 0.0;
+    for (int64_t i = 1; i < M; ++i) {
+        double den = b[i - 1] + (i >= 2 ? A[i - 2] * l[i - 1] : 0.0);
+        if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
+        l[i] = -A[i - 1] / den;
+        max_ratio = std::max(max_ratio, fabs(l[i]));
+    }
+    for (int64_t i = M - 2; i >= 0; --i) {
+        double den = b[i + 1] + (i + 2 <= M - 1 ? A[i + 1] * r[i + 1] : 0.0);
+        if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
+        r[i] = -A[i] / den;
+        max_ratio = std::max(max_ratio, fabs(r[i]));
+    }
+    o.max_ratio = max_ratio;
+
+    o.diag_inv.assign(M, 0.0);
+    for (int64_t k = 0; k < M; ++k) {
+        double den = b[k] + (k > 0 ? A[k - 1] * l[k] : 0.0) + (k + 1 < M ? A[k] * r[k] : 0.0);
+        if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
+        o.diag_inv[k] = 1.0 / den;
+    }
+
+    // Theorem 4's dominance condition (reported, not required)
+    bool dom = true, strict = false;
+    for (int64_t i = 0; i < M; ++i) {
+        double off = (i > 0 ? fabs(A[i - 1]) : 0.0) + (i + 1 < M ? fabs(A[i]) : 0.0);
+        if (fabs(b[i]) < off) dom = false;
+        if (fabs(b[i]) > off) strict = true;
+    }
+    o.dominant = (dom && strict) ? 1 : 0;
+
+    // weights of eq. beta_symn: the rows G_k of A^{-1} at the interface
+    // rows k = s_1..s_{P-1} over the two segments that touch k.  As in the
+    // paper's preliminary step, each G_k is the solution of A G_k = e_k by a
+    // sweep.  (The closed form g_k = 1/(b_k + a_{k-1} l_k + a_k r_k) loses
+    // digits to cancellation when A is close to singular -- about 1e-11
+    // relative for the 4096-row Poisson matrix -- and the interface values,
+    // sums of terms much larger than the solution, amplify that error.)
+    o.wR.assign(M, 0.0);
+    o.wL.assign(M, 0.0);
+    const auto& s = o.starts;
+    const bool by_sweep = (double)M * (double)(P - 1) <= 4.0e9;
+    std::vector<double> piv(M), cpg(M), dg(M), xg(M);
+    for (int64_t i = 0; i < M; ++i) {           // one forward factorization for all k
+        piv[i] = b[i] - (i > 0 ? A[i - 1] * cpg[i - 1] : 0.0);
+        if (piv[i] == 0.0 || bad(piv[i])) return TDS_ESINGULAR;
+        cpg[i] = (i + 1 < M) ? A[i] / piv[i] : 0.0;
+    }
+    for (int32_t j = 1; j < P; ++j) {
+        const int64_t k = s[j];
+        const int64_t lo = s[j - 1], hi = s[j + 1];   // rows of segments j-1 and j
+        if (by_sweep) {
+            // forward elimination of e_k: zero above k
+            dg[k] = 1.0 / piv[k];
+            for (int64_t i = k + 1; i < M; ++i) dg[i] = -A[i - 1] * dg[i - 1] / piv[i];
+            double x = dg[M - 1];
+            xg[M - 1] = x;
+            for (int64_t i = M - 2; i >= lo; --i) {
+                x = (i >= k ? dg[i] : 0.0) - cpg[i] * x;
+                xg[i] = x;
+            }
+        } else {
+            xg[k] = o.diag_inv[k];
+            for (int64_t i = k - 1; i >= lo; --i) xg[i] = xg[i + 1] * l[i + 1];
+            for (int64_t i = k + 1; i < hi; ++i) xg[i] = xg[i - 1] * r[i - 1];
+        }
+        if (bad(xg[k])) return TDS_ESINGULAR;
+        o.diag_inv[k] = xg[k];
+        for (int64_t i = lo; i < k; ++i) o.wR[i] = xg[i];      // segment j-1, right row k
+        for (int64_t i = k; i < hi; ++i) o.wL[i] = xg[i];      // segment j, left row k
+    }
+
+    // transfer factors between neighbouring interface rows
+    o.rho.assign(P, 0.0);
+    o.lam.assign(P, 0.0);
+    for (int32_t k = 1; k + 1 <= P - 1; ++k) {
+        double pr = 1.0, pl = 1.0;
+        for (int64_t m = s[k]; m < s[k + 1]; ++m) pr *= r[m];
+        for (int64_t m = s[k] + 1; m <= s[k + 1]; ++m) pl *= l[m];
+        o.rho[k] = pr;
+        o.lam[k] = pl;
+    }
+
+    // block-restarted elimination of every block's interior rows
+    o.cp64.assign(M, 0.0);
+    o.rd64.assign(M, 0.0);
+    for (int32_t j = 0; j < P; ++j) {
+        const int64_t i0 = (j == 0) ? s[0] : s[j] + 1;
+        const int64_t i1 = s[j + 1] - 1;
+        double cprev = 0.0;
+        for (int64_t i = i0; i <= i1; ++i) {
+            double den = b[i] - (i > i0 ? A[i - 1] * cprev : 0.0);
+            if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
+            o.rd64[i] = 1.0 / den;
+            o.cp64[i] = (i < i1) ? A[i] / den : 0.0;
+            cprev = o.cp64[i];
+        }
+    }
+    return TDS_OK;
+}
+
+}  // namespace tds

@@ -1,0 +1,294 @@
+"""Python binding of libtdsolve.so (ctypes).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.
+If the shared library is missing this module raises on first use; there is
+no CPU fallback.
+
+Arrays use the library's RHS-interleaved layout: a tensor of shape (M, N)
+whose column n is right-hand side n (row-major, contiguous).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdsolve.so")
+
+MODES = {"f64": 0, "f32_refined": 1, "f32": 2, "f32_wide": 3}
+_F_DTYPE = {0: "float64", 1: "float32", 2: "float32", 3: "float32"}
+_X_DTYPE = {0: "float64", 1: "float64", 2: "float32", 3: "float64"}
+
+SYMBOLS = [
+    "tdsolve_prepare", "tdsolve_series", "tdsolve_components", "tdsolve_backward",
+    "tdsolve_residual", "tdsolve_set_refinement", "tdsolve_info", "tdsolve_prepare_host",
+    "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
+    "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
+    "tdsolve_timing_read",
+]
+
+_lib = None
+
+
+class TdsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.tdsolve_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (status {code})")
+        self.code = code
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("P", ctypes.c_int32), ("max_block", ctypes.c_int32),
+                ("dominant", ctypes.c_int32), ("refine_passes", ctypes.c_int32),
+                ("max_ratio", ctypes.c_double)]
+
+
+def lib():
+    """Load libtdsolve.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c "
+                           "'import __graft_entry__ as g; g.build()'` (no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    L.tdsolve_prepare.argtypes = [dp, dp, i64, i32, ctypes.POINTER(vp)]
+    L.tdsolve_series.argtypes = [vp, vp, vp, i64, i32, vp]
+    L.tdsolve_components.argtypes = [vp, vp, vp, i64, i32, vp]
+    L.tdsolve_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp]
+    L.tdsolve_residual.argtypes = [vp, vp, vp, i64, i32, vp, vp]
+    L.tdsolve_set_refinement.argtypes = [vp, i32]
+    L.tdsolve_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.tdsolve_prepare_host.argtypes = [dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
+    L.tdsolve_default_blocks.argtypes = [i64]
+    L.tdsolve_default_blocks.restype = i32
+    L.tdsolve_destroy.argtypes = [vp]
+    L.tdsolve_strerror.argtypes = [ctypes.c_int]
+    L.tdsolve_strerror.restype = ctypes.c_char_p
+    L.tdsolve_batch_prepare.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.tdsolve_batch_series.argtypes = [vp, vp, vp, vp, i32, vp]
+    L.tdsolve_timing_enable.argtypes = [vp, i32]
+    L.tdsolve_timing_read.argtypes = [vp, vp, vp]
+    for name in SYMBOLS:
+        if name not in ("tdsolve_default_blocks", "tdsolve_strerror"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise TdsError(code, where)
+
+
+def _host_f64(x) -> np.ndarray:
+    if hasattr(x, "detach"):
+        x = x.detach().to("cpu").numpy()
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _ptr(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def mode_id(mode) -> int:
+    if isinstance(mode, str):
+        return MODES[mode]
+    return int(mode)
+
+
+def default_blocks(M: int) -> int:
+    return int(lib().tdsolve_default_blocks(M))
+
+
+def prepare_host(a, b, P: int):
+    """FP64 tables of the preliminary step computed on the host (no GPU)."""
+    L = lib()
+    b = _host_f64(b)
+    M = b.shape[0]
+    a = _host_f64(a) if M > 1 else np.zeros(1)
+    if P == 0:
+        P = default_blocks(M)
+    starts = np.zeros(P + 1, dtype=np.int64)
+    wR, wL, dinv = np.zeros(M), np.zeros(M), np.zeros(M)
+    rho, lam = np.zeros(P), np.zeros(P)
+    _check(L.tdsolve_prepare_host(_ptr(a), _ptr(b), M, P, _ptr(starts), _ptr(wR), _ptr(wL),
+                                  _ptr(rho), _ptr(lam), _ptr(dinv)), "tdsolve_prepare_host")
+    return dict(starts=starts, wR=wR, wL=wL, rho=rho, lam=lam, diag_inv=dinv, P=P, M=M)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A prepared matrix (preliminary step of the method, done once)."""
+
+    def __init__(self, a, b, P: Optional[int] = None):
+        L = lib()
+        b = _host_f64(b)
+        M = int(b.shape[0])
+        a = _host_f64(a) if M > 1 else np.zeros(1)
+        h = ctypes.c_void_p()
+        _check(L.tdsolve_prepare(_ptr(a), _ptr(b), M, int(P or 0), ctypes.byref(h)),
+               "tdsolve_prepare")
+        self._h = h
+        self.M = M
+        info = self.info()
+        self.P = info.P
+
+    def info(self) -> Info:
+        out = Info()
+        _check(lib().tdsolve_info(self._h, ctypes.byref(out)), "tdsolve_info")
+        return out
+
+    def timing(self, on: bool = True):
+        _check(lib().tdsolve_timing_enable(self._h, int(bool(on))), "tdsolve_timing_enable")
+
+    def timing_read(self):
+        """(ms_beta, ms_interface, ms_sweep, calls) accumulated since the last read."""
+        ms = np.zeros(3)
+        calls = np.zeros(1, dtype=np.int64)
+        _check(lib().tdsolve_timing_read(self._h, _ptr(ms), _ptr(calls)), "tdsolve_timing_read")
+        return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
+
+    def set_refinement(self, passes: int):
+        _check(lib().tdsolve_set_refinement(self._h, int(passes)), "tdsolve_set_refinement")
+
+    def _check_tensor(self, t, dtype: str, name: str, rows: Optional[int] = None):
+        import torch
+        want = getattr(torch, dtype)
+        rows = self.M if rows is None else rows
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != want:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if t.dim() != 2 or t.shape[0] != rows or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous ({rows}, N) tensor")
+
+    def solve(self, F, X=None, mode=None, stream=None):
+        """X = A^{-1} F for every column of F (device tensors, (M, N))."""
+        import torch
+        m = mode_id(mode if mode is not None else ("f64" if F.dtype == torch.float64 else "f32_refined"))
+        self._check_tensor(F, _F_DTYPE[m], "F")
+        N = F.shape[1]
+        if X is None:
+            X = torch.empty((self.M, N), dtype=getattr(torch, _X_DTYPE[m]), device=F.device)
+        self._check_tensor(X, _X_DTYPE[m], "X")
+        if X.shape[1] != N:
+            raise ValueError("X and F differ in N")
+        _check(lib().tdsolve_series(self._h, ctypes.c_void_p(F.data_ptr()),
+                                    ctypes.c_void_p(X.data_ptr()), N, m, _stream_ptr(stream)),
+               "tdsolve_series")
+        return X
+
+    def components(self, F, mode=None, stream=None):
+        """Algorithm 3 alone: x at the P-1 interface rows, shape (P-1, N), FP64."""
+        import torch
+        m = mode_id(mode if mode is not None else ("f64" if F.dtype == torch.float64 else "f32_refined"))
+        self._check_tensor(F, _F_DTYPE[m], "F")
+        N = F.shape[1]
+        out = torch.empty((max(self.P - 1, 0), N), dtype=torch.float64, device=F.device)
+        if self.P > 1 and N > 0:
+            _check(lib().tdsolve_components(self._h, ctypes.c_void_p(F.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), N, m,
+                                            _stream_ptr(stream)), "tdsolve_components")
+        return out
+
+    def residual(self, F, X, mode=None, stream=None):
+        """(eta, r2) per right-hand side, each an FP64 device tensor of N."""
+        import torch
+        m = mode_id(mode if mode is not None else ("f64" if F.dtype == torch.float64 else "f32_refined"))
+        self._check_tensor(F, _F_DTYPE[m], "F")
+        self._check_tensor(X, _X_DTYPE[m], "X")
+        N = F.shape[1]
+        out = torch.zeros(2 * N, dtype=torch.float64, device=F.device)
+        _check(lib().tdsolve_residual(self._h, ctypes.c_void_p(F.data_ptr()),
+                                      ctypes.c_void_p(X.data_ptr()), N, m,
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "tdsolve_residual")
+        return out[:N], out[N:]
+
+    def backward(self, X, gX, mode=None, want_ga=True, want_gb=True, stream=None):
+        """Adjoint: (gF, ga, gb) for dL/dX = gX at the solution X."""
+        import torch
+        m = mode_id(mode if mode is not None else ("f64" if X.dtype == torch.float64 else "f32"))
+        self._check_tensor(X, _X_DTYPE[m], "X")
+        self._check_tensor(gX, _X_DTYPE[m], "gX")
+        N = X.shape[1]
+        gF = torch.empty((self.M, N), dtype=getattr(torch, _F_DTYPE[m]), device=X.device)
+        ga = torch.empty(max(self.M - 1, 0), dtype=torch.float64, device=X.device) if want_ga else None
+        gb = torch.empty(self.M, dtype=torch.float64, device=X.device) if want_gb else None
+        pga = ctypes.c_void_p(ga.data_ptr()) if (ga is not None and ga.numel()) else None
+        pgb = ctypes.c_void_p(gb.data_ptr()) if gb is not None else None
+        _check(lib().tdsolve_backward(self._h, ctypes.c_void_p(X.data_ptr()),
+                                      ctypes.c_void_p(gX.data_ptr()),
+                                      ctypes.c_void_p(gF.data_ptr()), pga, pgb, N, m,
+                                      _stream_ptr(stream)), "tdsolve_backward")
+        return gF, ga, gb
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tdsolve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd_fn():
+    import torch
+
+    class TDSolveFn(torch.autograd.Function):
+        """X = A(a, b)^{-1} F with gradients for F, a and b.
+
+        The backward pass reuses the forward's prepared plan: A is symmetric,
+        so gF = A^{-1} gX is another solve with the same tables (Lemma 2)."""
+
+        @staticmethod
+        def forward(ctx, F, a, b, P=None, mode=None):
+            plan = Plan(a, b, P)
+            m = mode_id(mode if mode is not None else ("f64" if F.dtype == torch.float64 else "f32_refined"))
+            X = plan.solve(F.contiguous(), mode=m)
+            ctx.plan, ctx.mode = plan, m
+            ctx.a_meta = (a.dtype, a.device)
+            ctx.b_meta = (b.dtype, b.device)
+            ctx.save_for_backward(X)
+            return X
+
+        @staticmethod
+        def backward(ctx, gX):
+            (X,) = ctx.saved_tensors
+            need_F, need_a, need_b = ctx.needs_input_grad[:3]
+            gF, ga, gb = ctx.plan.backward(X, gX.contiguous().to(X.dtype), mode=ctx.mode,
+                                           want_ga=need_a, want_gb=need_b)
+            ga = ga.to(dtype=ctx.a_meta[0], device=ctx.a_meta[1]) if (need_a and ga is not None) else None
+            gb = gb.to(dtype=ctx.b_meta[0], device=ctx.b_meta[1]) if (need_b and gb is not None) else None
+            return (gF if need_F else None), ga, gb, None, None
+
+    return TDSolveFn
+
+
+_TDSolveFn = None
+
+
+def TDSolveFn():
+    global _TDSolveFn
+    if _TDSolveFn is None:
+        _TDSolveFn = _autograd_fn()
+    return _TDSolveFn
+
+
+def tdsolve(F, a, b, P=None, mode=None):
+    """Differentiable solve of the series A(a, b) X = F."""
+    return TDSolveFn().apply(F, a, b, P, mode)
