@@ -35,35 +35,44 @@ int upload(tds_plan* h) {
     const HostTables& o = h->host;
     const int64_t M = o.M;
     const int32_t P = o.P;
+    // row tables carry kRegMaxRows + 1 padding rows (a = cp = 0, b = rd = 1)
+    // so that the register sweep's phantom rows always read in bounds
+    const int64_t MR = M + kRegMaxRows + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     const size_t o_starts = take(sizeof(int64_t) * (P + 1));
-    const size_t o_wR = take(sizeof(double) * M), o_wL = take(sizeof(double) * M);
+    const size_t o_wR = take(sizeof(double) * MR), o_wL = take(sizeof(double) * MR);
     const size_t o_rho = take(sizeof(double) * P), o_lam = take(sizeof(double) * P);
-    const size_t o_a64 = take(sizeof(double) * M), o_b64 = take(sizeof(double) * M);
-    const size_t o_cp64 = take(sizeof(double) * M), o_rd64 = take(sizeof(double) * M);
-    const size_t o_a32 = take(sizeof(float) * M), o_cp32 = take(sizeof(float) * M);
-    const size_t o_rd32 = take(sizeof(float) * M);
+    const size_t o_a64 = take(sizeof(double) * MR), o_b64 = take(sizeof(double) * MR);
+    const size_t o_cp64 = take(sizeof(double) * MR), o_rd64 = take(sizeof(double) * MR);
+    const size_t o_a32 = take(sizeof(float) * MR), o_cp32 = take(sizeof(float) * MR);
+    const size_t o_rd32 = take(sizeof(float) * MR);
     const size_t total = off;
 
     std::vector<unsigned char> img(total, 0);
     auto put = [&](size_t at, const void* src, size_t bytes) { memcpy(img.data() + at, src, bytes); };
+    auto pad64 = [&](size_t at, const std::vector<double>& v, double fill) {
+        std::vector<double> t(v.begin(), v.end());
+        t.resize(MR, fill);
+        put(at, t.data(), sizeof(double) * MR);
+    };
+    auto pad32 = [&](size_t at, const std::vector<double>& v, float fill) {
+        std::vector<float> t(MR, fill);
+        for (int64_t i = 0; i < M; ++i) t[i] = (float)v[i];
+        put(at, t.data(), sizeof(float) * MR);
+    };
     put(o_starts, o.starts.data(), sizeof(int64_t) * (P + 1));
-    put(o_wR, o.wR.data(), sizeof(double) * M);
-    put(o_wL, o.wL.data(), sizeof(double) * M);
+    pad64(o_wR, o.wR, 0.0);
+    pad64(o_wL, o.wL, 0.0);
     put(o_rho, o.rho.data(), sizeof(double) * P);
     put(o_lam, o.lam.data(), sizeof(double) * P);
-    put(o_a64, o.a64.data(), sizeof(double) * M);
-    put(o_b64, o.b64.data(), sizeof(double) * M);
-    put(o_cp64, o.cp64.data(), sizeof(double) * M);
-    put(o_rd64, o.rd64.data(), sizeof(double) * M);
-    std::vector<float> f(M);
-    for (int64_t i = 0; i < M; ++i) f[i] = (float)o.a64[i];
-    put(o_a32, f.data(), sizeof(float) * M);
-    for (int64_t i = 0; i < M; ++i) f[i] = (float)o.cp64[i];
-    put(o_cp32, f.data(), sizeof(float) * M);
-    for (int64_t i = 0; i < M; ++i) f[i] = (float)o.rd64[i];
-    put(o_rd32, f.data(), sizeof(float) * M);
+    pad64(o_a64, o.a64, 0.0);
+    pad64(o_b64, o.b64, 1.0);
+    pad64(o_cp64, o.cp64, 0.0);
+    pad64(o_rd64, o.rd64, 1.0);
+    pad32(o_a32, o.a64, 0.0f);
+    pad32(o_cp32, o.cp64, 0.0f);
+    pad32(o_rd32, o.rd64, 1.0f);
 
     if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
     void* mem = nullptr;
@@ -111,6 +120,8 @@ int ensure_work(tds_plan* h, size_t bytes) {
     return TDS_OK;
 }
 
+char* general_of(tds_plan* h) { return (char*)h->work; }
+
 bool valid_mode(int32_t m) { return m >= TDS_F64 && m <= TDS_F32_WIDE; }
 size_t f_elem(int32_t m) { return m == TDS_F64 ? 8 : 4; }
 size_t x_elem(int32_t m) { return m == TDS_F32 ? 4 : 8; }
@@ -122,7 +133,7 @@ int check_common(tds_plan* h, int64_t N, int32_t mode) {
     return TDS_OK;
 }
 
-// beta + interface step into xsep; work layout: betaR | betaL | xsep(optional)
+// beta + interface step into xsep
 int interface_step(tds_plan* h, const void* F, int64_t N, int32_t mode, double* xsep,
                    double* betaR, double* betaL, hipStream_t s) {
     const DevTables& t = h->dev;
@@ -148,12 +159,12 @@ int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hi
                 int sweep_mode) {
     const DevTables& t = h->dev;
     const int64_t P = t.P;
-    const size_t nb = sizeof(double) * (size_t)P * (size_t)N;
-    int rc = ensure_work(h, align256(nb) * 2 + align256(sizeof(double) * (size_t)(P > 1 ? P - 1 : 1) * N));
+    const size_t nb = align256(sizeof(double) * (size_t)P * (size_t)N);
+    int rc = ensure_work(h, 2 * nb + align256(sizeof(double) * (size_t)(P > 1 ? P - 1 : 1) * N));
     if (rc) return rc;
-    double* betaR = (double*)h->work;
-    double* betaL = (double*)((char*)h->work + align256(nb));
-    double* xsep = (double*)((char*)h->work + 2 * align256(nb));
+    double* betaR = (double*)general_of(h);
+    double* betaL = (double*)(general_of(h) + nb);
+    double* xsep = (double*)(general_of(h) + 2 * nb);
     hipEvent_t* ev = timing_slot(h);
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TDS_EHIP;
     if (t.P >= 2) {
@@ -215,11 +226,11 @@ int tdsolve_components(tds_handle h, const void* F, double* Xsep, int64_t N, int
     if (rc) return rc;
     if (N == 0 || h->dev.P < 2) return TDS_OK;
     if (!F || !Xsep) return TDS_EINVAL;
-    const size_t nb = sizeof(double) * (size_t)h->dev.P * (size_t)N;
-    rc = ensure_work(h, align256(nb) * 2);
+    const size_t nb = align256(sizeof(double) * (size_t)h->dev.P * (size_t)N);
+    rc = ensure_work(h, nb * 2);
     if (rc) return rc;
-    double* betaR = (double*)h->work;
-    double* betaL = (double*)((char*)h->work + align256(nb));
+    double* betaR = (double*)general_of(h);
+    double* betaL = (double*)(general_of(h) + nb);
     return interface_step(h, F, N, mode, Xsep, betaR, betaL, (hipStream_t)stream);
 }
 
@@ -276,7 +287,7 @@ int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N, int3
     if (chunks > 65535) return TDS_EUNSUPPORTED;
     rc = ensure_work(h, sizeof(double) * 5 * (size_t)chunks * (size_t)N);
     if (rc) return rc;
-    if (launch_residual(h->dev, F, X, N, mode, h->normA, (double*)h->work, out,
+    if (launch_residual(h->dev, F, X, N, mode, h->normA, (double*)general_of(h), out,
                         (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
     return TDS_OK;

@@ -6,8 +6,9 @@
 // the RHS-interleaved layout F[i*N + n], every row access of a wavefront is
 // one contiguous 256 B (FP32) or 512 B (FP64) span: loads and stores
 // coalesce without any transposition.  The coefficients of the constant
-// matrix are the same for every lane, so the sweep stages its block's rows
-// of them in LDS and every lane reads them as broadcasts.
+// matrix are the same for every lane: the beta kernel stages its block's
+// weights in LDS, the sweep reads its coefficients through scalar loads;
+// either way every lane gets them as broadcasts.
 //
 //   k_beta   eq. beta_symn: beta^R_j, beta^L_j of block j (FP64 accumulation).
 //   k_iface  Theorem 2 (eq. theor_2): x at the interface rows by the two
@@ -22,10 +23,14 @@ namespace tds {
 
 enum SweepKind { kSweep64 = 0, kSweepRefined = 1, kSweep32 = 2 };
 
+
 // --------------------------------------------------------------------------
-// beta weights (eq. beta_symn).  The weight arrays are read with
-// wave-uniform addresses, which the compiler turns into scalar loads.
-template <typename Fin>
+// beta weights (eq. beta_symn).  Workgroup (tile, j): block j of rows x 256
+// consecutive right-hand sides, one per lane.  All rows of the block are
+// loaded before any arithmetic (one round trip to memory per workgroup);
+// rows past the block re-read its last row and get weight zero.  The
+// weights are wave-uniform and come in through scalar loads.
+template <int TMAX, typename Fin>
 __global__ __launch_bounds__(kWG) void k_beta(const Fin* __restrict__ F, int64_t N, int32_t P,
                                               const int64_t* __restrict__ starts,
                                               const double* __restrict__ wR,
@@ -38,49 +43,113 @@ __global__ __launch_bounds__(kWG) void k_beta(const Fin* __restrict__ F, int64_t
     const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (n >= N) return;
     const Fin* f = F + lo * N + n;
+    const double* __restrict__ gR = wR + lo;
+    const double* __restrict__ gL = wL + lo;
     double bR = 0.0, bL = 0.0;
-    int r = 0;
-    for (; r + 8 <= t; r += 8) {
-        Fin v[8];
+    if (TMAX > 0 && t <= TMAX) {
+        Fin v[TMAX > 0 ? TMAX : 1];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = f[(int64_t)(r + u) * N];
+        for (int r = 0; r < TMAX; ++r) v[r] = f[(int64_t)(r < t ? r : t - 1) * N];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double x = (double)v[u];
-            bR = fma(wR[lo + r + u], x, bR);
-            bL = fma(wL[lo + r + u], x, bL);
+        for (int r = 0; r < TMAX; ++r) {
+            const double a = (r < t) ? gR[r] : 0.0;
+            const double c = (r < t) ? gL[r] : 0.0;
+            bR = fma(a, (double)v[r], bR);
+            bL = fma(c, (double)v[r], bL);
         }
-    }
-    for (; r < t; ++r) {
-        const double x = (double)f[(int64_t)r * N];
-        bR = fma(wR[lo + r], x, bR);
-        bL = fma(wL[lo + r], x, bL);
+    } else {
+        constexpr int U = 16;
+        int r = 0;
+        for (; r + U <= t; r += U) {
+            Fin v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = f[(int64_t)(r + u) * N];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                bR = fma(gR[r + u], (double)v[u], bR);
+                bL = fma(gL[r + u], (double)v[u], bL);
+            }
+        }
+        for (; r < t; ++r) {
+            const double v = (double)f[(int64_t)r * N];
+            bR = fma(gR[r], v, bR);
+            bL = fma(gL[r], v, bL);
+        }
     }
     if (j < P - 1) betaR[(int64_t)j * N + n] = bR;
     if (j > 0) betaL[(int64_t)j * N + n] = bL;
 }
 
 // --------------------------------------------------------------------------
-// interface rows (Theorem 2).  xsep row k-1 holds x(s_k), k = 1..P-1.
-__global__ __launch_bounds__(kWG) void k_iface(int64_t N, int32_t P,
-                                               const double* __restrict__ rho,
-                                               const double* __restrict__ lam,
-                                               const double* __restrict__ betaR,
-                                               const double* __restrict__ betaL,
-                                               double* __restrict__ xsep) {
-    const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (n >= N) return;
-    double SR = betaR[n];                     // S^R_1 = beta^R_0
-    xsep[n] = SR;
-    for (int32_t k = 1; k <= P - 2; ++k) {    // S^R_{k+1}
-        SR = fma(rho[k], SR, betaR[(int64_t)k * N + n]);
-        xsep[(int64_t)k * N + n] = SR;
+// Interface step (Theorem 2): the O(P) recurrences
+//   forward   y_j = rho_j y_{j-1} + beta^R_j,  j = 0..P-2 (y_{-1} = 0),
+//             so that S^R_{k} = y_{k-1};
+//   backward  z_j = lam_j z_{j+1} + beta^L_j,  j = P-1..1 (z_P = 0),
+//             so that S^L_k = z_k;
+//   x(s_k) = S^R_k + S^L_k, k = 1..P-1  (xsep row k-1),
+// evaluated as a two-level scan: workgroup = 64 right-hand sides x G groups
+// of consecutive blocks; each thread scans its group with zero input, the
+// group carries (product of the factors, partial value) are combined through
+// LDS, then each thread redoes its group with the true input.
+constexpr int kScanRhs = 64;
+constexpr int kScanMaxGroups = 16;
+
+__global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface(
+    int64_t N, int32_t P, int32_t per, const double* __restrict__ rho,
+    const double* __restrict__ lam, const double* __restrict__ betaR,
+    const double* __restrict__ betaL, double* __restrict__ xsep) {
+    __shared__ double s_carry[2][kScanMaxGroups][kScanRhs];
+    __shared__ double s_prod[2][kScanMaxGroups];
+    const int lane = threadIdx.x % kScanRhs;
+    const int g = threadIdx.x / kScanRhs;
+    const int64_t n = (int64_t)blockIdx.x * kScanRhs + lane;
+    const bool live = n < N;
+    // forward groups over j = 0..P-2, backward groups over j = 1..P-1
+    const int32_t f0 = g * per, f1 = min(f0 + per, P - 1);
+    const int32_t b1 = P - 1 - g * per, b0 = max(b1 - per, 0);   // j in (b0, b1]
+
+    double yl = 0.0, pr = 1.0;
+#pragma unroll 4
+    for (int32_t j = f0; j < f1; ++j) {
+        const double r = (j > 0) ? rho[j] : 0.0;
+        yl = fma(r, yl, live ? betaR[(int64_t)j * N + n] : 0.0);
+        pr *= r;
     }
-    double SL = betaL[(int64_t)(P - 1) * N + n];   // S^L_{P-1} = beta^L_{P-1}
-    xsep[(int64_t)(P - 2) * N + n] += SL;
-    for (int32_t k = P - 2; k >= 1; --k) {    // S^L_k
-        SL = fma(lam[k], SL, betaL[(int64_t)k * N + n]);
-        xsep[(int64_t)(k - 1) * N + n] += SL;
+    double zl = 0.0, pl = 1.0;
+#pragma unroll 4
+    for (int32_t j = b1; j > b0; --j) {
+        const double l = (j < P - 1) ? lam[j] : 0.0;
+        zl = fma(l, zl, live ? betaL[(int64_t)j * N + n] : 0.0);
+        pl *= l;
+    }
+    s_carry[0][g][lane] = yl;
+    s_carry[1][g][lane] = zl;
+    if (lane == 0) {
+        s_prod[0][g] = (f0 < f1) ? pr : 1.0;
+        s_prod[1][g] = (b0 < b1) ? pl : 1.0;
+    }
+    __syncthreads();
+    double yin = 0.0, zin = 0.0;
+    for (int q = 0; q < g; ++q) yin = fma(s_prod[0][q], yin, s_carry[0][q][lane]);
+    for (int q = 0; q < g; ++q) zin = fma(s_prod[1][q], zin, s_carry[1][q][lane]);
+    // redo the forward group with its true input: y_j = S^R_{j+1} into xsep
+    if (live) {
+        double y = yin;
+#pragma unroll 4
+        for (int32_t j = f0; j < f1; ++j) {
+            const double r = (j > 0) ? rho[j] : 0.0;
+            y = fma(r, y, betaR[(int64_t)j * N + n]);
+            xsep[(int64_t)j * N + n] = y;
+        }
+    }
+    __syncthreads();    // S^R of every group is in xsep (same workgroup)
+    if (!live) return;
+    double z = zin;
+#pragma unroll 4
+    for (int32_t j = b1; j > b0; --j) {
+        const double l = (j < P - 1) ? lam[j] : 0.0;
+        z = fma(l, z, betaL[(int64_t)j * N + n]);
+        xsep[(int64_t)(j - 1) * N + n] += z;           // x(s_j) = S^R_j + S^L_j
     }
 }
 
@@ -90,42 +159,59 @@ __global__ __launch_bounds__(kWG) void k_iface(int64_t N, int32_t P,
 // are solved with x at the interface rows s_j (left) and s_{j+1} (right)
 // known.  Each lane keeps its whole column of the block in VGPRs: F is read
 // once and X written once.
-template <int TMAX>
-struct SweepLDS {
-    double sub[TMAX], diag[TMAX], sup[TMAX], cp[TMAX], rd[TMAX];
-    float sub32[TMAX], cp32[TMAX], rd32[TMAX];
+//
+// The coefficients are the same for every lane; they are read through
+// wave-uniform addresses, i.e. scalar loads into SGPRs through the scalar
+// cache, which broadcast to the wavefront without occupying VGPRs or LDS
+// (staging them in LDS instead costs VGPRs for every value in flight and an
+// LDS round trip per row; the scalar path measured fewer registers).
+//
+// One kernel serves every block length cnt <= TMAX: rows cnt..TMAX-1 are
+// "phantom" rows.  They re-read the block's last real row of F and the
+// (padded, always in-bounds) coefficient tables, so their values stay
+// finite, and they never feed back into real rows because the last real
+// row's elimination factor cp and its super-diagonal entry are zero.  They
+// are not stored.  The only per-row conditions are uniform scalar ones.
+struct BlockCoef {
+    // tables offset to the block's first interior row i0; valid up to
+    // i0 + TMAX (the device tables carry kRegMaxRows padding rows)
+    const double* __restrict__ a64;
+    const double* __restrict__ b64;
+    const double* __restrict__ cp64;
+    const double* __restrict__ rd64;
+    const float* __restrict__ a32;
+    const float* __restrict__ cp32_;
+    const float* __restrict__ rd32_;
+    int cnt;
+    __device__ double sub(int r) const { return r > 0 ? a64[r - 1] : 0.0; }
+    __device__ double sup(int r) const { return r < cnt - 1 ? a64[r] : 0.0; }
+    __device__ double diag(int r) const { return b64[r]; }
+    __device__ double cp(int r) const { return cp64[r]; }
+    __device__ double rd(int r) const { return rd64[r]; }
+    __device__ float sub32(int r) const { return r > 0 ? a32[r - 1] : 0.0f; }
+    __device__ float cp32(int r) const { return cp32_[r]; }
+    __device__ float rd32(int r) const { return rd32_[r]; }
 };
 
-// The row count CNT is a template constant for the common block sizes, so
-// the unrolled row loops carry no per-row conditions; CNT == 0 takes the
-// count at run time (rows past it are skipped by uniform branches).
-template <int TMAX, int CNT, typename Fin, typename Xout, int KIND>
+template <int TMAX, typename Fin, typename Xout, int KIND>
 __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __restrict__ xp,
-                                           int64_t N, int cnt_rt, double cl, double xl,
-                                           double cr, double xr, const SweepLDS<TMAX>& L,
+                                           int64_t N, int cnt, double cl, double xl,
+                                           double cr, double xr, const BlockCoef& L,
                                            float* __restrict__ my_f, int passes) {
-    const int cnt = (CNT == 0) ? cnt_rt : CNT;
-#define TDS_ACTIVE(r) ((CNT == 0) ? ((r) < cnt) : ((r) < CNT))
     Fin f[TMAX];
-    {
-        const Fin* q = fp;
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            if (TDS_ACTIVE(r)) f[r] = *q;
-            q += N;
-        }
-    }
+    for (int r = 0; r < TMAX; ++r) f[r] = fp[(int64_t)(r < cnt ? r : cnt - 1) * N];
     if constexpr (KIND == kSweepRefined) {
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r)
-            if (TDS_ACTIVE(r)) my_f[r * kWG] = (float)f[r];
+        for (int r = 0; r < TMAX; ++r) my_f[r * kWG] = (float)f[r];
     }
+    const double clxl = cl * xl, crxr = cr * xr;
 
     // right-hand side of block row r with the known boundary values moved over
     auto g = [&](int r) -> double {
         double v = (KIND == kSweepRefined) ? (double)my_f[r * kWG] : (double)f[r];
-        if (r == 0) v -= cl * xl;
-        if (r == cnt - 1) v -= cr * xr;
+        if (r == 0) v -= clxl;
+        if (r == cnt - 1) v -= crxr;
         return v;
     };
 
@@ -133,38 +219,30 @@ __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __r
         double d[TMAX];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
-            if (TDS_ACTIVE(r)) {
-                const double prev = (r > 0) ? d[r - 1] : 0.0;
-                d[r] = (g(r) - L.sub[r] * prev) * L.rd[r];
-            }
+            const double prev = (r > 0) ? d[r - 1] : 0.0;
+            d[r] = (g(r) - L.sub(r) * prev) * L.rd(r);
         }
         double x = 0.0;
         Xout* q = xp + (int64_t)(TMAX - 1) * N;
 #pragma unroll
         for (int r = TMAX - 1; r >= 0; --r) {
-            if (TDS_ACTIVE(r)) {
-                x = d[r] - L.cp[r] * x;
-                *q = (Xout)x;
-            }
+            x = d[r] - L.cp(r) * x;
+            if (r < cnt) *q = (Xout)x;
             q -= N;
         }
     } else if constexpr (KIND == kSweep32) {
         float w[TMAX];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
-            if (TDS_ACTIVE(r)) {
-                const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                w[r] = ((float)g(r) - L.sub32[r] * prev) * L.rd32[r];
-            }
+            const float prev = (r > 0) ? w[r - 1] : 0.0f;
+            w[r] = ((float)g(r) - L.sub32(r) * prev) * L.rd32(r);
         }
         float x = 0.0f;
         Xout* q = xp + (int64_t)(TMAX - 1) * N;
 #pragma unroll
         for (int r = TMAX - 1; r >= 0; --r) {
-            if (TDS_ACTIVE(r)) {
-                x = w[r] - L.cp32[r] * x;
-                *q = (Xout)x;
-            }
+            x = w[r] - L.cp32(r) * x;
+            if (r < cnt) *q = (Xout)x;
             q -= N;
         }
     } else {
@@ -174,87 +252,74 @@ __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __r
         float w[TMAX];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
-            if (TDS_ACTIVE(r)) {
-                const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                w[r] = ((float)g(r) - L.sub32[r] * prev) * L.rd32[r];
-            }
+            if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+            const float prev = (r > 0) ? w[r - 1] : 0.0f;
+            w[r] = ((float)g(r) - L.sub32(r) * prev) * L.rd32(r);
         }
         {
             float xs = 0.0f;
 #pragma unroll
             for (int r = TMAX - 1; r >= 0; --r) {
-                if (TDS_ACTIVE(r)) {
-                    xs = w[r] - L.cp32[r] * xs;
-                    x[r] = (double)xs;
-                } else {
-                    x[r] = 0.0;
-                }
+                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                xs = w[r] - L.cp32(r) * xs;
+                x[r] = (double)xs;
             }
         }
         for (int p = 0; p < passes; ++p) {
-            // keep the LDS reads inside the pass: hoisting them out of the
-            // loop would hold every row's coefficients in VGPRs
+            // keep the LDS reads of F inside the pass
             asm volatile("" ::: "memory");
+            const BlockCoef& Lp = L;
 #pragma unroll
             for (int r = 0; r < TMAX; ++r) {
-                if (TDS_ACTIVE(r)) {
-                    double res = g(r) - L.diag[r] * x[r];
-                    if (r > 0) res -= L.sub[r] * x[r - 1];
-                    if (r + 1 < TMAX) res -= L.sup[r] * x[r + 1];
-                    const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                    w[r] = ((float)res - L.sub32[r] * prev) * L.rd32[r];
-                }
+                // bound the scheduler's look-ahead: the residuals do not
+                // depend on the elimination chain, and computing them all
+                // ahead of it would hold 64 FP64 values in registers
+                if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+                double res = g(r) - Lp.diag(r) * x[r];
+                if (r > 0) res -= Lp.sub(r) * x[r - 1];
+                if (r + 1 < TMAX) res -= Lp.sup(r) * x[r + 1];
+                const float prev = (r > 0) ? w[r - 1] : 0.0f;
+                w[r] = ((float)res - Lp.sub32(r) * prev) * Lp.rd32(r);
             }
             float dl = 0.0f;
 #pragma unroll
             for (int r = TMAX - 1; r >= 0; --r) {
-                if (TDS_ACTIVE(r)) {
-                    dl = w[r] - L.cp32[r] * dl;
-                    x[r] += (double)dl;
-                }
+                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                dl = w[r] - Lp.cp32(r) * dl;
+                x[r] += (double)dl;
             }
         }
         Xout* q = xp;
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
-            if (TDS_ACTIVE(r)) *q = (Xout)x[r];
+            if (r < cnt) *q = (Xout)x[r];
             q += N;
         }
     }
-#undef TDS_ACTIVE
 }
 
+// The refined sweep needs about 3 registers per row (x in FP64, the FP32
+// elimination value) and keeps F in LDS; two waves per SIMD is its target.
+template <int KIND>
+constexpr int sweep_min_waves() { return KIND == kSweepRefined ? 2 : 1; }
+
 template <int TMAX, typename Fin, typename Xout, int KIND>
-__global__ __launch_bounds__(kWG) void k_sweep_reg(
+__global__ __launch_bounds__(kWG, sweep_min_waves<KIND>()) void k_sweep_reg(
     const Fin* __restrict__ F, Xout* __restrict__ X, int64_t N, int32_t P,
     const int64_t* __restrict__ starts, const double* __restrict__ a64,
     const double* __restrict__ b64, const double* __restrict__ cp64,
     const double* __restrict__ rd64, const float* __restrict__ a32,
     const float* __restrict__ cp32, const float* __restrict__ rd32,
     const double* __restrict__ xsep, int passes) {
-    __shared__ SweepLDS<TMAX> L;
     // the refined sweep keeps its FP32 input column in LDS (one row of 256
-    // lanes per block row, conflict-free) so its VGPRs hold only x and the
-    // FP32 elimination values
+    // lanes per block row, conflict-free) so that its VGPRs hold only x and
+    // the FP32 elimination values
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
 
     const int32_t j = blockIdx.y;
     const int64_t seg_lo = starts[j], seg_hi = starts[j + 1];
     const int64_t i0 = (j == 0) ? seg_lo : seg_lo + 1;
     const int cnt = (int)(seg_hi - i0);
-    for (int r = threadIdx.x; r < cnt; r += kWG) {
-        const int64_t i = i0 + r;
-        L.sub[r] = (r > 0) ? a64[i - 1] : 0.0;
-        L.sup[r] = (r < cnt - 1) ? a64[i] : 0.0;
-        L.diag[r] = b64[i];
-        L.cp[r] = cp64[i];
-        L.rd[r] = rd64[i];
-        L.sub32[r] = (r > 0) ? a32[i - 1] : 0.0f;
-        L.cp32[r] = cp32[i];
-        L.rd32[r] = rd32[i];
-    }
-    __syncthreads();
-
     const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (n >= N) return;
     const double xl = (j > 0) ? xsep[(int64_t)(j - 1) * N + n] : 0.0;
@@ -263,16 +328,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_reg(
     const double cr = (j < P - 1) ? a64[seg_hi - 1] : 0.0; // A[i1][i1+1]
     if (j > 0) X[seg_lo * N + n] = (Xout)xl;
 
-    const Fin* fp = F + i0 * N + n;
-    Xout* xp = X + i0 * N + n;
-    float* my_f = s_f + threadIdx.x;
-    if (cnt == TMAX)
-        sweep_body<TMAX, TMAX, Fin, Xout, KIND>(fp, xp, N, cnt, cl, xl, cr, xr, L, my_f, passes);
-    else if (cnt == TMAX - 1)
-        sweep_body<TMAX, TMAX - 1, Fin, Xout, KIND>(fp, xp, N, cnt, cl, xl, cr, xr, L, my_f,
-                                                    passes);
-    else
-        sweep_body<TMAX, 0, Fin, Xout, KIND>(fp, xp, N, cnt, cl, xl, cr, xr, L, my_f, passes);
+    const BlockCoef C{a64 + i0, b64 + i0, cp64 + i0, rd64 + i0, a32 + i0, cp32 + i0, rd32 + i0,
+                      cnt};
+    sweep_body<TMAX, Fin, Xout, KIND>(F + i0 * N + n, X + i0 * N + n, N, cnt, cl, xl, cr, xr, C,
+                                      s_f + threadIdx.x, passes);
 }
 
 // --------------------------------------------------------------------------
@@ -421,24 +480,44 @@ static inline dim3 grid2(int64_t N, int64_t y) {
     return dim3((unsigned)((N + kWG - 1) / kWG), (unsigned)y, 1);
 }
 
-hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N,
-                       double* betaR, double* betaL, hipStream_t s) {
-    if (t.P < 2 || N == 0) return hipSuccess;
-    dim3 g = grid2(N, t.P);
-    if (f32)
-        hipLaunchKernelGGL(k_beta<float>, g, dim3(kWG), 0, s, (const float*)F, N, t.P,
+template <typename Fin>
+static void go_beta(const DevTables& t, const void* F, int64_t N, double* betaR, double* betaL,
+                    hipStream_t s) {
+    const dim3 g = grid2(N, t.P);
+    const int m = t.max_rows;
+    if (m <= 32)
+        hipLaunchKernelGGL((k_beta<32, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
+                           t.starts, t.wR, t.wL, betaR, betaL);
+    else if (m <= 64)
+        hipLaunchKernelGGL((k_beta<64, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
+                           t.starts, t.wR, t.wL, betaR, betaL);
+    else if (m <= 128)
+        hipLaunchKernelGGL((k_beta<128, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
                            t.starts, t.wR, t.wL, betaR, betaL);
     else
-        hipLaunchKernelGGL(k_beta<double>, g, dim3(kWG), 0, s, (const double*)F, N, t.P,
+        hipLaunchKernelGGL((k_beta<0, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
                            t.starts, t.wR, t.wL, betaR, betaL);
+}
+
+hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
+                       double* betaL, hipStream_t s) {
+    if (t.P < 2 || N == 0) return hipSuccess;
+    if (f32)
+        go_beta<float>(t, F, N, betaR, betaL, s);
+    else
+        go_beta<double>(t, F, N, betaR, betaL, s);
     return hipGetLastError();
 }
 
 hipError_t launch_iface(const DevTables& t, const double* betaR, const double* betaL,
                         double* xsep, int64_t N, hipStream_t s) {
     if (t.P < 2 || N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_iface, grid2(N, 1), dim3(kWG), 0, s, N, t.P, t.rho, t.lam, betaR,
-                       betaL, xsep);
+    const int32_t nsep = t.P - 1;
+    int32_t per = (nsep + kScanMaxGroups - 1) / kScanMaxGroups;
+    if (per < 4) per = 4;
+    const int32_t G = (nsep + per - 1) / per;
+    hipLaunchKernelGGL(k_iface, dim3((unsigned)((N + kScanRhs - 1) / kScanRhs)),
+                       dim3(kScanRhs * G), 0, s, N, t.P, per, t.rho, t.lam, betaR, betaL, xsep);
     return hipGetLastError();
 }
 

@@ -14,9 +14,11 @@ accurate to (t + P) u.  Per right-hand side n we therefore require
         <= 1e-11 + 8 (t + 2P) u cond_n,
     cond_n = max_k sum_i |G_k(i)| |F_i,n| / |X_or,n|_inf,
 
-for the FP64-result modes, and, where the residual kernel is checked, the
-relative residual r2 = |F - A X|_2 / |F|_2 <= 1e-10 (the accuracy target of
-the series solve).  The FP32-result mode is held to 2e-4 relative error on
+for the FP64-result modes, and, where the residual kernel is checked, a
+relative residual r2 = |F - A X|_2 / |F|_2 within 1e-10 of the oracle's own
+(the accuracy target of the series solve: r2_n <= r2_or,n + 1e-10; a plain
+FP64 sweep already reaches r2 ~ 1e-10 on the Poisson columns that carry the
+lowest sine mode, so an absolute 1e-10 cannot be the reading).  The FP32-result mode is held to 2e-4 relative error on
 well-conditioned cases (FP32 rounding times the condition number).
 """
 import numpy as np
@@ -66,6 +68,13 @@ def _assert_parity(X, ref, tol, what):
     e = _col_err(X, ref)
     bad = np.nonzero(e > tol)[0]
     assert bad.size == 0, f"{what}: columns {bad[:5]} e={e[bad[:5]]} tol={tol[bad[:5]]}"
+
+
+def _r2(a, b, F, X):
+    R = F - b[:, None] * X
+    R[:-1] -= a[:, None] * X[1:]
+    R[1:] -= a[:, None] * X[:-1]
+    return np.linalg.norm(R, axis=0) / np.maximum(np.linalg.norm(F, axis=0), 1e-300)
 
 
 def _solve_all_modes(a, b, F64, P):
@@ -148,33 +157,31 @@ def test_poisson_series_reduced_refined_meets_gates():
     eta, r2 = plan.residual(Fs, X, mode="f32_refined")
     Xh = X.cpu().numpy()
     _assert_parity(Xh, ref, _tol64(a, b, Fw, ref, 64), "f32_refined")
-    assert float(r2.max()) <= TOL64
+    r2_or = _r2(a, b, Fw, ref)
+    assert np.all(r2.cpu().numpy() <= r2_or + TOL64)
     m = method.residual_metrics(a, b, Fw, Xh, ref)
-    assert m["r2"] <= TOL64 and abs(m["r2"] - float(r2.max())) <= 1e-3 * m["r2"] + 1e-18
+    assert abs(m["r2"] - float(r2.max())) <= 1e-3 * m["r2"] + 1e-18
     assert abs(m["eta"] - float(eta.max())) <= 1e-3 * m["eta"] + 1e-20
 
 
-def test_poisson_series_full_size_sampled():
+def test_poisson_series_full_size():
     # full 4096 x 4096 workload in the launch configuration the benchmark
-    # times; the oracle checks a sample of columns, the residual kernel all
+    # times, every column against the oracle
     w = wl.poisson_series()
     a, b, F32 = w["a"], w["b"], w["F"]
+    Fw = F32.astype(np.float64)
+    ref = oracle.thomas(a, b, Fw)
+    tol = _tol64(a, b, Fw, ref, w["P"])
+    r2_or = _r2(a, b, Fw, ref)
     plan = t.Plan(a, b, w["P"])
     Fs = torch.from_numpy(F32).to(DEV)
-    for mode in ("f32_refined", "f32_wide"):
-        X = plan.solve(Fs, mode=mode)
-        eta, r2 = plan.residual(Fs, X, mode=mode)
-        assert float(r2.max()) <= TOL64, mode
-        cols = np.random.default_rng(0).choice(w["N"], size=48, replace=False)
-        cols = np.concatenate([cols, [0, w["N"] - 1]])
-        Fc = F32[:, cols].astype(np.float64)
-        ref = oracle.thomas(a, b, Fc)
-        _assert_parity(X[:, torch.from_numpy(cols).to(DEV)].cpu().numpy(), ref,
-                       _tol64(a, b, Fc, ref, w["P"]), mode)
-    Fd = Fs.double()
-    X = plan.solve(Fd, mode="f64")
-    eta, r2 = plan.residual(Fd, X, mode="f64")
-    assert float(r2.max()) <= TOL64
+    for mode, Fin in (("f32_refined", Fs), ("f32_wide", Fs), ("f64", Fs.double())):
+        print(f"full size mode={mode}", flush=True)
+        X = plan.solve(Fin, mode=mode)
+        eta, r2 = plan.residual(Fin, X, mode=mode)
+        assert np.all(r2.cpu().numpy() <= r2_or + TOL64), mode
+        _assert_parity(X.cpu().numpy(), ref, tol, mode)
+        del X
 
 
 def test_bitwise_reproducible():
