@@ -34,9 +34,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--mode", default="f32_refined",
                    choices=["f32_refined", "f64", "f32_wide", "f32"])
-    p.add_argument("--M", type=int, default=4096)
-    p.add_argument("--N", type=int, default=4096)
-    p.add_argument("--P", type=int, default=64)
+    p.add_argument("--workload", default="poisson", choices=["poisson", "adi"],
+                   help="poisson: 1-D Poisson series 4096x4096, P=64 (default); "
+                        "adi: ADI line solves 8192x8192, b=2.05, P=128")
+    p.add_argument("--M", type=int, default=0)
+    p.add_argument("--N", type=int, default=0)
+    p.add_argument("--P", type=int, default=0)
     p.add_argument("--sets", type=int, default=0,
                    help="buffer sets rotated across steps (0: enough to exceed 512 MB)")
     p.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison runs")
@@ -81,8 +84,14 @@ def main():
     from paper_0901_2859_amd import tdsolve as t
     from paper_0901_2859_amd import workloads as wl
 
-    M, N, P = args.M, args.N, args.P
-    w = wl.poisson_series(M=M, N=N, P=P)
+    if args.workload == "poisson":
+        M, N, P = args.M or 4096, args.N or 4096, args.P or 64
+        w = wl.poisson_series(M=M, N=N, P=P)
+        wname = "1-D Poisson series (sum of 8 sine modes + noise), FP32 storage with FP64 refinement"
+    else:
+        M, N, P = args.M or 8192, args.N or 8192, args.P or 128
+        w = wl.adi_lines(M=M, N=N, P=P)
+        wname = "ADI line solves on a smooth Gaussian random field (b=2.05), FP32 storage"
     a, b, F32 = w["a"], w["b"], w["F"]
     dev = torch.device("cuda:0")
     plan = t.Plan(a, b, P)
@@ -165,8 +174,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"f32_refined": "f32+f64", "f64": "f64", "f32_wide": "f32->f64", "f32": "f32"}[args.mode],
         "data": "synthetic",
-        "config": {"workload": "1-D Poisson series (sum of 8 sine modes + noise), FP32 storage "
-                               "with FP64 refinement", "M": M, "N": N, "P": P,
+        "config": {"workload": wname, "M": M, "N": N, "P": P,
                    "mode": args.mode, "layout": "RHS-interleaved [M][N]",
                    "buffer_sets": main_r["sets"]},
         "hbm_frac_path": round(main_r["path_gbs"] / HBM_PEAK_GBS, 4),

@@ -45,8 +45,14 @@ int upload(tds_plan* h) {
     const size_t o_rho = take(sizeof(double) * P), o_lam = take(sizeof(double) * P);
     const size_t o_a64 = take(sizeof(double) * MR), o_b64 = take(sizeof(double) * MR);
     const size_t o_cp64 = take(sizeof(double) * MR), o_rd64 = take(sizeof(double) * MR);
+    // beta weights of every block, zero-padded to the register kernel's row
+    // count, so that rows past a block's end weigh nothing
+    const int32_t WP = o.max_rows <= 32 ? 32 : o.max_rows <= 64 ? 64 : o.max_rows <= 128 ? 128 : 0;
+    const size_t o_wpad = take(sizeof(double) * 2 * (size_t)P * (size_t)(WP > 0 ? WP : 1));
+    const size_t o_in64 = take(sizeof(double) * MR), o_u = take(sizeof(double) * MR);
+    const size_t o_v = take(sizeof(double) * MR);
     const size_t o_a32 = take(sizeof(float) * MR), o_cp32 = take(sizeof(float) * MR);
-    const size_t o_rd32 = take(sizeof(float) * MR);
+    const size_t o_rd32 = take(sizeof(float) * MR), o_in32 = take(sizeof(float) * MR);
     const size_t total = off;
 
     std::vector<unsigned char> img(total, 0);
@@ -70,10 +76,27 @@ int upload(tds_plan* h) {
     pad64(o_b64, o.b64, 1.0);
     pad64(o_cp64, o.cp64, 0.0);
     pad64(o_rd64, o.rd64, 1.0);
-    pad32(o_a32, o.a64, 0.0f);
-    pad32(o_cp32, o.cp64, 0.0f);
-    pad32(o_rd32, o.rd64, 1.0f);
-
+    if (WP > 0) {
+        std::vector<double> wp(2 * (size_t)P * WP, 0.0);
+        for (int32_t j = 0; j < P; ++j)
+            for (int64_t i = o.starts[j]; i < o.starts[j + 1]; ++i) {
+                const size_t r = (size_t)j * WP + (size_t)(i - o.starts[j]);
+                wp[2 * r] = o.wR[i];
+                wp[2 * r + 1] = o.wL[i];
+            }
+        put(o_wpad, wp.data(), sizeof(double) * wp.size());
+    }
+    {
+        std::vector<double> in(o.a64);
+        for (int32_t j = 0; j < P; ++j) in[o.starts[j + 1] - 1] = 0.0;   // block ends
+        pad64(o_in64, in, 0.0);
+        pad64(o_u, o.u, 0.0);
+        pad64(o_v, o.v, 0.0);
+        pad32(o_a32, o.a64, 0.0f);
+        pad32(o_cp32, o.cp64, 0.0f);
+        pad32(o_rd32, o.rd64, 1.0f);
+        pad32(o_in32, in, 0.0f);
+    }
     if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, total);
@@ -98,9 +121,15 @@ int upload(tds_plan* h) {
     d.b64 = (double*)(base + o_b64);
     d.cp64 = (double*)(base + o_cp64);
     d.rd64 = (double*)(base + o_rd64);
+    d.wpad = (const double2*)(base + o_wpad);
+    d.wpad_rows = WP;
+    d.in64 = (double*)(base + o_in64);
+    d.u = (double*)(base + o_u);
+    d.v = (double*)(base + o_v);
     d.a32 = (float*)(base + o_a32);
     d.cp32 = (float*)(base + o_cp32);
     d.rd32 = (float*)(base + o_rd32);
+    d.in32 = (float*)(base + o_in32);
     return TDS_OK;
 }
 

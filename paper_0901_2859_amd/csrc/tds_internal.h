@@ -19,7 +19,8 @@ constexpr int kWG = 256;
 constexpr int kRegMaxRows = 128;
 
 // Device tables of one prepared matrix (all FP64 unless noted).  Row arrays
-// have M entries.  `starts` has P+1 entries (s_0 = 0 .. s_P = M).
+// have M entries (plus padding rows, see the upload).  `starts` has P+1
+// entries (s_0 = 0 .. s_P = M).
 struct DevTables {
     int64_t M = 0;
     int32_t P = 0;
@@ -33,6 +34,17 @@ struct DevTables {
     double* b64 = nullptr;     // b[i]
     double* cp64 = nullptr;    // block-restarted elimination: x_i + cp_i x_{i+1} = d_i
     double* rd64 = nullptr;    // 1 / pivot
+    // Block-interior coupling a[i] to row i+1, zero at every block's last
+    // interior row (so a block's zero-boundary system ends there); serves as
+    // the super-diagonal of row i and, read at i-1, the sub-diagonal of row i.
+    double* in64 = nullptr;
+    float* in32 = nullptr;
+    // Block responses to the interface values: x = x0 + xl u + xr v, with
+    // u = T^{-1}(-a_{i0-1} e_first), v = T^{-1}(-a_{i1} e_last) (Lemma 1).
+    double* u = nullptr;
+    double* v = nullptr;
+    const double2* wpad = nullptr;         // beta weights (wR, wL) per block,
+    int32_t wpad_rows = 0;                 //   padded to wpad_rows with zeros
     float* a32 = nullptr;
     float* cp32 = nullptr;
     float* rd32 = nullptr;
@@ -46,7 +58,7 @@ struct HostTables {
     int32_t dominant = 0;
     double max_ratio = 0.0;
     std::vector<int64_t> starts;
-    std::vector<double> wR, wL, rho, lam, diag_inv, a64, b64, cp64, rd64;
+    std::vector<double> wR, wL, rho, lam, diag_inv, a64, b64, cp64, rd64, u, v;
 };
 
 int host_prepare(const double* a, const double* b, int64_t M, int32_t P,

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(kWG) void k_beta(const Fin* __restrict__ F, int64_t
                                               const int64_t* __restrict__ starts,
                                               const double* __restrict__ wR,
                                               const double* __restrict__ wL,
+                                              const double2* __restrict__ wpad,
                                               double* __restrict__ betaR,
                                               double* __restrict__ betaL) {
     const int32_t j = blockIdx.y;
@@ -43,21 +44,22 @@ __global__ __launch_bounds__(kWG) void k_beta(const Fin* __restrict__ F, int64_t
     const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (n >= N) return;
     const Fin* f = F + lo * N + n;
-    const double* __restrict__ gR = wR + lo;
-    const double* __restrict__ gL = wL + lo;
     double bR = 0.0, bL = 0.0;
-    if (TMAX > 0 && t <= TMAX) {
-        Fin v[TMAX > 0 ? TMAX : 1];
+    if constexpr (TMAX > 0) {
+        // weights zero-padded per block: rows past the end add nothing
+        const double2* __restrict__ w = wpad + (int64_t)j * TMAX;
+        Fin v[TMAX];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) v[r] = f[(int64_t)(r < t ? r : t - 1) * N];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
-            const double a = (r < t) ? gR[r] : 0.0;
-            const double c = (r < t) ? gL[r] : 0.0;
-            bR = fma(a, (double)v[r], bR);
-            bL = fma(c, (double)v[r], bL);
+            const double2 c = w[r];
+            bR = fma(c.x, (double)v[r], bR);
+            bL = fma(c.y, (double)v[r], bL);
         }
     } else {
+        const double* __restrict__ gR = wR + lo;
+        const double* __restrict__ gL = wL + lo;
         constexpr int U = 16;
         int r = 0;
         for (; r + U <= t; r += U) {
@@ -156,22 +158,22 @@ __global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface(
 // --------------------------------------------------------------------------
 // Block sweep, register-resident.  Block j's interior rows i0..i1 (block 0
 // starts at row 0; the others at the row after their left interface row)
-// are solved with x at the interface rows s_j (left) and s_{j+1} (right)
-// known.  Each lane keeps its whole column of the block in VGPRs: F is read
-// once and X written once.
+// are solved with x at the interface rows s_j (left, xl) and s_{j+1}
+// (right, xr) known (Lemma 1).  Each lane keeps its whole column of the
+// block in VGPRs: F is read once and X written once.
 //
 // The coefficients are the same for every lane; they are read through
 // wave-uniform addresses, i.e. scalar loads into SGPRs through the scalar
-// cache, which broadcast to the wavefront without occupying VGPRs or LDS
-// (staging them in LDS instead costs VGPRs for every value in flight and an
-// LDS round trip per row; the scalar path measured fewer registers).
+// cache, which broadcast to the wavefront without occupying VGPRs.  The
+// tables are separate arrays so that each sweep fetches only the bytes it
+// uses (the scalar fetch volume per row shows directly in the run time).
 //
 // One kernel serves every block length cnt <= TMAX: rows cnt..TMAX-1 are
 // "phantom" rows.  They re-read the block's last real row of F and the
-// (padded, always in-bounds) coefficient tables, so their values stay
+// (padded, always in-bounds) table rows that follow, so their values stay
 // finite, and they never feed back into real rows because the last real
-// row's elimination factor cp and its super-diagonal entry are zero.  They
-// are not stored.  The only per-row conditions are uniform scalar ones.
+// row's elimination factor and block-interior coupling are zero.  They are
+// not stored.
 struct BlockCoef {
     // tables offset to the block's first interior row i0; valid up to
     // i0 + TMAX (the device tables carry kRegMaxRows padding rows)
@@ -179,137 +181,156 @@ struct BlockCoef {
     const double* __restrict__ b64;
     const double* __restrict__ cp64;
     const double* __restrict__ rd64;
+    const double* __restrict__ in64;
+    const double* __restrict__ u;
+    const double* __restrict__ v;
     const float* __restrict__ a32;
-    const float* __restrict__ cp32_;
-    const float* __restrict__ rd32_;
-    int cnt;
-    __device__ double sub(int r) const { return r > 0 ? a64[r - 1] : 0.0; }
-    __device__ double sup(int r) const { return r < cnt - 1 ? a64[r] : 0.0; }
-    __device__ double diag(int r) const { return b64[r]; }
-    __device__ double cp(int r) const { return cp64[r]; }
-    __device__ double rd(int r) const { return rd64[r]; }
-    __device__ float sub32(int r) const { return r > 0 ? a32[r - 1] : 0.0f; }
-    __device__ float cp32(int r) const { return cp32_[r]; }
-    __device__ float rd32(int r) const { return rd32_[r]; }
+    const float* __restrict__ cp32;
+    const float* __restrict__ rd32;
+    const float* __restrict__ in32;
 };
 
 template <int TMAX, typename Fin, typename Xout, int KIND>
 __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __restrict__ xp,
-                                           int64_t N, int cnt, double cl, double xl,
-                                           double cr, double xr, const BlockCoef& L,
+                                           int64_t N, int cnt, double cl, double xl, double cr,
+                                           double xr, const BlockCoef& L,
                                            float* __restrict__ my_f, int passes) {
     Fin f[TMAX];
 #pragma unroll
     for (int r = 0; r < TMAX; ++r) f[r] = fp[(int64_t)(r < cnt ? r : cnt - 1) * N];
-    if constexpr (KIND == kSweepRefined) {
-#pragma unroll
-        for (int r = 0; r < TMAX; ++r) my_f[r * kWG] = (float)f[r];
-    }
-    const double clxl = cl * xl, crxr = cr * xr;
 
-    // right-hand side of block row r with the known boundary values moved over
-    auto g = [&](int r) -> double {
-        double v = (KIND == kSweepRefined) ? (double)my_f[r * kWG] : (double)f[r];
-        if (r == 0) v -= clxl;
-        if (r == cnt - 1) v -= crxr;
-        return v;
-    };
-
-    if constexpr (KIND == kSweep64) {
-        double d[TMAX];
+    if constexpr (KIND == kSweep64 || KIND == kSweep32) {
+        // one pass: the known boundary values are moved to the right-hand
+        // side of the block's first and last interior rows
+        const double clxl = cl * xl, crxr = cr * xr;
+        auto g = [&](int r) -> double {
+            double val = (double)f[r];
+            if (r == 0) val -= clxl;
+            if (r == cnt - 1) val -= crxr;
+            return val;
+        };
+        if constexpr (KIND == kSweep64) {
+            double d[TMAX];
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            const double prev = (r > 0) ? d[r - 1] : 0.0;
-            d[r] = (g(r) - L.sub(r) * prev) * L.rd(r);
-        }
-        double x = 0.0;
-        Xout* q = xp + (int64_t)(TMAX - 1) * N;
+            for (int r = 0; r < TMAX; ++r) {
+                const double prev = (r > 0) ? d[r - 1] : 0.0;
+                const double sub = (r > 0) ? L.a64[r - 1] : 0.0;
+                d[r] = (g(r) - sub * prev) * L.rd64[r];
+            }
+            double x = 0.0;
+            Xout* q = xp + (int64_t)(TMAX - 1) * N;
 #pragma unroll
-        for (int r = TMAX - 1; r >= 0; --r) {
-            x = d[r] - L.cp(r) * x;
-            if (r < cnt) *q = (Xout)x;
-            q -= N;
-        }
-    } else if constexpr (KIND == kSweep32) {
-        float w[TMAX];
+            for (int r = TMAX - 1; r >= 0; --r) {
+                x = d[r] - L.cp64[r] * x;
+                if (r < cnt) *q = (Xout)x;
+                q -= N;
+            }
+        } else {
+            float w[TMAX];
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            const float prev = (r > 0) ? w[r - 1] : 0.0f;
-            w[r] = ((float)g(r) - L.sub32(r) * prev) * L.rd32(r);
-        }
-        float x = 0.0f;
-        Xout* q = xp + (int64_t)(TMAX - 1) * N;
+            for (int r = 0; r < TMAX; ++r) {
+                const float prev = (r > 0) ? w[r - 1] : 0.0f;
+                const float sub = (r > 0) ? L.a32[r - 1] : 0.0f;
+                w[r] = ((float)g(r) - sub * prev) * L.rd32[r];
+            }
+            float x = 0.0f;
+            Xout* q = xp + (int64_t)(TMAX - 1) * N;
 #pragma unroll
-        for (int r = TMAX - 1; r >= 0; --r) {
-            x = w[r] - L.cp32(r) * x;
-            if (r < cnt) *q = (Xout)x;
-            q -= N;
+            for (int r = TMAX - 1; r >= 0; --r) {
+                x = w[r] - L.cp32[r] * x;
+                if (r < cnt) *q = (Xout)x;
+                q -= N;
+            }
         }
     } else {
-        // FP32 sweep, then `passes` times: FP64 residual of the block
-        // system -> FP32 sweep of the residual -> FP64 update.
+        // Refined: the block is solved with zero boundary values, x0 =
+        // T^{-1} f, by an FP32 sweep and then `passes` times FP64 residual
+        // -> FP32 sweep of the residual -> FP64 update; the interface values
+        // enter at the end by superposition, x = x0 + xl u + xr v.  (With
+        // the boundary terms inside the right-hand side every pass would
+        // carry a row-dependent condition.)
+#pragma unroll
+        for (int r = 0; r < TMAX; ++r) my_f[r * kWG] = (float)f[r];
         double x[TMAX];
         float w[TMAX];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
             if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
             const float prev = (r > 0) ? w[r - 1] : 0.0f;
-            w[r] = ((float)g(r) - L.sub32(r) * prev) * L.rd32(r);
+            const float sub = (r > 0) ? L.in32[r - 1] : 0.0f;
+            w[r] = (my_f[r * kWG] - sub * prev) * L.rd32[r];
         }
         {
             float xs = 0.0f;
 #pragma unroll
             for (int r = TMAX - 1; r >= 0; --r) {
                 if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                xs = w[r] - L.cp32(r) * xs;
+                xs = w[r] - L.cp32[r] * xs;
                 x[r] = (double)xs;
             }
         }
         for (int p = 0; p < passes; ++p) {
-            // keep the LDS reads of F inside the pass
+            // keep the LDS reads of F and the table loads inside the pass:
+            // an offset the compiler cannot see through stops it from
+            // hoisting every row's coefficients out of the loop
             asm volatile("" ::: "memory");
-            const BlockCoef& Lp = L;
+            int z;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+            const double* __restrict__ in64 = L.in64 + z;
+            const double* __restrict__ b64 = L.b64 + z;
+            const float* __restrict__ in32 = L.in32 + z;
+            const float* __restrict__ cp32 = L.cp32 + z;
+            const float* __restrict__ rd32 = L.rd32 + z;
 #pragma unroll
             for (int r = 0; r < TMAX; ++r) {
                 // bound the scheduler's look-ahead: the residuals do not
                 // depend on the elimination chain, and computing them all
                 // ahead of it would hold 64 FP64 values in registers
                 if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
-                double res = g(r) - Lp.diag(r) * x[r];
-                if (r > 0) res -= Lp.sub(r) * x[r - 1];
-                if (r + 1 < TMAX) res -= Lp.sup(r) * x[r + 1];
+                double res = (double)my_f[r * kWG] - b64[r] * x[r];
+                if (r > 0) res -= in64[r - 1] * x[r - 1];
+                if (r + 1 < TMAX) res -= in64[r] * x[r + 1];
                 const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                w[r] = ((float)res - Lp.sub32(r) * prev) * Lp.rd32(r);
+                const float sub = (r > 0) ? in32[r - 1] : 0.0f;
+                w[r] = ((float)res - sub * prev) * rd32[r];
             }
             float dl = 0.0f;
 #pragma unroll
             for (int r = TMAX - 1; r >= 0; --r) {
                 if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                dl = w[r] - Lp.cp32(r) * dl;
+                dl = w[r] - cp32[r] * dl;
                 x[r] += (double)dl;
             }
         }
         Xout* q = xp;
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
-            if (r < cnt) *q = (Xout)x[r];
+            if (r < cnt) *q = (Xout)fma(xr, L.v[r], fma(xl, L.u[r], x[r]));
             q += N;
         }
     }
 }
 
-// The refined sweep needs about 3 registers per row (x in FP64, the FP32
-// elimination value) and keeps F in LDS; two waves per SIMD is its target.
-template <int KIND>
-constexpr int sweep_min_waves() { return KIND == kSweepRefined ? 2 : 1; }
+// Occupancy target (waves per SIMD) of the refined sweep, which holds about
+// 3 registers per row (x in FP64, the FP32 elimination value; F sits in
+// LDS); the other sweeps are left to the compiler.
+template <int KIND, int TMAX>
+constexpr int sweep_min_waves() {
+    return TMAX > 64 ? 1 : KIND == kSweepRefined ? 2 : 1;
+}
 
+// (The tables come in as separate __restrict__ parameters, not as one
+// struct: only then can the compiler prove them unaliased by the stores to X
+// and fetch them with scalar loads.)
 template <int TMAX, typename Fin, typename Xout, int KIND>
-__global__ __launch_bounds__(kWG, sweep_min_waves<KIND>()) void k_sweep_reg(
+__global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_reg(
     const Fin* __restrict__ F, Xout* __restrict__ X, int64_t N, int32_t P,
     const int64_t* __restrict__ starts, const double* __restrict__ a64,
     const double* __restrict__ b64, const double* __restrict__ cp64,
-    const double* __restrict__ rd64, const float* __restrict__ a32,
-    const float* __restrict__ cp32, const float* __restrict__ rd32,
+    const double* __restrict__ rd64, const double* __restrict__ in64,
+    const double* __restrict__ u, const double* __restrict__ v,
+    const float* __restrict__ a32, const float* __restrict__ cp32,
+    const float* __restrict__ rd32, const float* __restrict__ in32,
     const double* __restrict__ xsep, int passes) {
     // the refined sweep keeps its FP32 input column in LDS (one row of 256
     // lanes per block row, conflict-free) so that its VGPRs hold only x and
@@ -324,12 +345,12 @@ __global__ __launch_bounds__(kWG, sweep_min_waves<KIND>()) void k_sweep_reg(
     if (n >= N) return;
     const double xl = (j > 0) ? xsep[(int64_t)(j - 1) * N + n] : 0.0;
     const double xr = (j < P - 1) ? xsep[(int64_t)j * N + n] : 0.0;
-    const double cl = (j > 0) ? a64[i0 - 1] : 0.0;        // A[i0][i0-1]
+    const double cl = (j > 0) ? a64[i0 - 1] : 0.0;         // A[i0][i0-1]
     const double cr = (j < P - 1) ? a64[seg_hi - 1] : 0.0; // A[i1][i1+1]
     if (j > 0) X[seg_lo * N + n] = (Xout)xl;
 
-    const BlockCoef C{a64 + i0, b64 + i0, cp64 + i0, rd64 + i0, a32 + i0, cp32 + i0, rd32 + i0,
-                      cnt};
+    const BlockCoef C{a64 + i0, b64 + i0, cp64 + i0, rd64 + i0, in64 + i0, u + i0,
+                      v + i0, a32 + i0, cp32 + i0, rd32 + i0, in32 + i0};
     sweep_body<TMAX, Fin, Xout, KIND>(F + i0 * N + n, X + i0 * N + n, N, cnt, cl, xl, cr, xr, C,
                                       s_f + threadIdx.x, passes);
 }
@@ -484,19 +505,23 @@ template <typename Fin>
 static void go_beta(const DevTables& t, const void* F, int64_t N, double* betaR, double* betaL,
                     hipStream_t s) {
     const dim3 g = grid2(N, t.P);
-    const int m = t.max_rows;
-    if (m <= 32)
-        hipLaunchKernelGGL((k_beta<32, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
-                           t.starts, t.wR, t.wL, betaR, betaL);
-    else if (m <= 64)
-        hipLaunchKernelGGL((k_beta<64, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
-                           t.starts, t.wR, t.wL, betaR, betaL);
-    else if (m <= 128)
-        hipLaunchKernelGGL((k_beta<128, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
-                           t.starts, t.wR, t.wL, betaR, betaL);
-    else
-        hipLaunchKernelGGL((k_beta<0, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
-                           t.starts, t.wR, t.wL, betaR, betaL);
+    switch (t.wpad_rows) {
+        case 32:
+            hipLaunchKernelGGL((k_beta<32, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
+                               t.starts, t.wR, t.wL, t.wpad, betaR, betaL);
+            break;
+        case 64:
+            hipLaunchKernelGGL((k_beta<64, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
+                               t.starts, t.wR, t.wL, t.wpad, betaR, betaL);
+            break;
+        case 128:
+            hipLaunchKernelGGL((k_beta<128, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
+                               t.starts, t.wR, t.wL, t.wpad, betaR, betaL);
+            break;
+        default:
+            hipLaunchKernelGGL((k_beta<0, Fin>), g, dim3(kWG), 0, s, (const Fin*)F, N, t.P,
+                               t.starts, t.wR, t.wL, t.wpad, betaR, betaL);
+    }
 }
 
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
@@ -526,7 +551,7 @@ static void go_reg(const DevTables& t, const void* F, void* X, int64_t N, int pa
                    const double* xsep, hipStream_t s) {
     hipLaunchKernelGGL((k_sweep_reg<TMAX, Fin, Xout, KIND>), grid2(N, t.P), dim3(kWG), 0, s,
                        (const Fin*)F, (Xout*)X, N, t.P, t.starts, t.a64, t.b64, t.cp64, t.rd64,
-                       t.a32, t.cp32, t.rd32, xsep, passes);
+                       t.in64, t.u, t.v, t.a32, t.cp32, t.rd32, t.in32, xsep, passes);
 }
 
 template <typename Fin, typename Xout, int KIND>

@@ -157,9 +157,12 @@ int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
         o.lam[k] = pl;
     }
 
-    // block-restarted elimination of every block's interior rows
+    // block-restarted elimination of every block's interior rows, and the
+    // block's responses u, v to its left / right interface value
     o.cp64.assign(M, 0.0);
     o.rd64.assign(M, 0.0);
+    o.u.assign(M, 0.0);
+    o.v.assign(M, 0.0);
     for (int32_t j = 0; j < P; ++j) {
         const int64_t i0 = (j == 0) ? s[0] : s[j] + 1;
         const int64_t i1 = s[j + 1] - 1;
@@ -171,6 +174,20 @@ int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
             o.cp64[i] = (i < i1) ? A[i] / den : 0.0;
             cprev = o.cp64[i];
         }
+        const double cl = (j > 0) ? A[i0 - 1] : 0.0;      // A[i0][i0-1]
+        const double cr = (j < P - 1) ? A[i1] : 0.0;      // A[i1][i1+1]
+        // u = T^{-1}(-cl e_first): forward elimination then back substitution
+        double d = -cl * o.rd64[i0];
+        o.u[i0] = d;
+        for (int64_t i = i0 + 1; i <= i1; ++i) {
+            d = (0.0 - A[i - 1] * d) * o.rd64[i];
+            o.u[i] = d;
+        }
+        for (int64_t i = i1 - 1; i >= i0; --i) o.u[i] -= o.cp64[i] * o.u[i + 1];
+        // v = T^{-1}(-cr e_last): only the last row is non-zero after the
+        // forward elimination
+        o.v[i1] = -cr * o.rd64[i1];
+        for (int64_t i = i1 - 1; i >= i0; --i) o.v[i] = -o.cp64[i] * o.v[i + 1];
     }
     return TDS_OK;
 }
