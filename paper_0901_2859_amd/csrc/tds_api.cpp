@@ -25,37 +25,43 @@ struct tds_plan {
     bool timing = false;         // record per-phase events
     std::vector<hipEvent_t> events;  // 4 per timed call
     size_t events_used = 0;
+    // batch handles: K matrices sharing one table allocation
+    bool is_batch = false;
+    int32_t bucket = 0;                  // common register-sweep row bucket
+    std::vector<HostTables> hosts;
+    std::vector<DevTables> devs;
+    std::vector<BatchDesc> desc;         // last descriptors uploaded
+    BatchDesc* d_desc = nullptr;
+    size_t desc_cap = 0;
 };
 
 namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int upload(tds_plan* h) {
-    const HostTables& o = h->host;
+// Append one matrix's device tables to a host image; the returned tables
+// hold byte offsets into the image in place of pointers (see rebase()).
+// Row tables carry kRegMaxRows + 1 padding rows (a = cp = 0, b = rd = 1) so
+// that the register sweep's phantom rows always read in bounds.  `WP` is
+// the row count the per-block beta weights are zero-padded to (0: none).
+DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned char>& img) {
     const int64_t M = o.M;
     const int32_t P = o.P;
-    // row tables carry kRegMaxRows + 1 padding rows (a = cp = 0, b = rd = 1)
-    // so that the register sweep's phantom rows always read in bounds
     const int64_t MR = M + kRegMaxRows + 1;
-    size_t off = 0;
+    size_t off = align256(img.size());
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     const size_t o_starts = take(sizeof(int64_t) * (P + 1));
     const size_t o_wR = take(sizeof(double) * MR), o_wL = take(sizeof(double) * MR);
     const size_t o_rho = take(sizeof(double) * P), o_lam = take(sizeof(double) * P);
     const size_t o_a64 = take(sizeof(double) * MR), o_b64 = take(sizeof(double) * MR);
     const size_t o_cp64 = take(sizeof(double) * MR), o_rd64 = take(sizeof(double) * MR);
-    // beta weights of every block, zero-padded to the register kernel's row
-    // count, so that rows past a block's end weigh nothing
-    const int32_t WP = o.max_rows <= 32 ? 32 : o.max_rows <= 64 ? 64 : o.max_rows <= 128 ? 128 : 0;
     const size_t o_wpad = take(sizeof(double) * 2 * (size_t)P * (size_t)(WP > 0 ? WP : 1));
     const size_t o_in64 = take(sizeof(double) * MR), o_u = take(sizeof(double) * MR);
     const size_t o_v = take(sizeof(double) * MR);
     const size_t o_a32 = take(sizeof(float) * MR), o_cp32 = take(sizeof(float) * MR);
     const size_t o_rd32 = take(sizeof(float) * MR), o_in32 = take(sizeof(float) * MR);
-    const size_t total = off;
+    img.resize(off, 0);
 
-    std::vector<unsigned char> img(total, 0);
     auto put = [&](size_t at, const void* src, size_t bytes) { memcpy(img.data() + at, src, bytes); };
     auto pad64 = [&](size_t at, const std::vector<double>& v, double fill) {
         std::vector<double> t(v.begin(), v.end());
@@ -77,6 +83,8 @@ int upload(tds_plan* h) {
     pad64(o_cp64, o.cp64, 0.0);
     pad64(o_rd64, o.rd64, 1.0);
     if (WP > 0) {
+        // beta weights of every block, zero-padded to the register kernel's
+        // row count, so that rows past a block's end weigh nothing
         std::vector<double> wp(2 * (size_t)P * WP, 0.0);
         for (int32_t j = 0; j < P; ++j)
             for (int64_t i = o.starts[j]; i < o.starts[j + 1]; ++i) {
@@ -86,50 +94,74 @@ int upload(tds_plan* h) {
             }
         put(o_wpad, wp.data(), sizeof(double) * wp.size());
     }
-    {
-        std::vector<double> in(o.a64);
-        for (int32_t j = 0; j < P; ++j) in[o.starts[j + 1] - 1] = 0.0;   // block ends
-        pad64(o_in64, in, 0.0);
-        pad64(o_u, o.u, 0.0);
-        pad64(o_v, o.v, 0.0);
-        pad32(o_a32, o.a64, 0.0f);
-        pad32(o_cp32, o.cp64, 0.0f);
-        pad32(o_rd32, o.rd64, 1.0f);
-        pad32(o_in32, in, 0.0f);
-    }
-    if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
-    void* mem = nullptr;
-    hipError_t e = hipMalloc(&mem, total);
-    if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
-    if (e != hipSuccess) return TDS_EHIP;
-    if (hipMemcpy(mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(mem);
-        return TDS_EHIP;
-    }
-    h->dev_mem = mem;
-    unsigned char* base = (unsigned char*)mem;
-    DevTables& d = h->dev;
+    std::vector<double> in(o.a64);
+    for (int32_t j = 0; j < P; ++j) in[o.starts[j + 1] - 1] = 0.0;   // block ends
+    pad64(o_in64, in, 0.0);
+    pad64(o_u, o.u, 0.0);
+    pad64(o_v, o.v, 0.0);
+    pad32(o_a32, o.a64, 0.0f);
+    pad32(o_cp32, o.cp64, 0.0f);
+    pad32(o_rd32, o.rd64, 1.0f);
+    pad32(o_in32, in, 0.0f);
+
+    DevTables d;
     d.M = M;
     d.P = P;
     d.max_rows = o.max_rows;
-    d.starts = (int64_t*)(base + o_starts);
-    d.wR = (double*)(base + o_wR);
-    d.wL = (double*)(base + o_wL);
-    d.rho = (double*)(base + o_rho);
-    d.lam = (double*)(base + o_lam);
-    d.a64 = (double*)(base + o_a64);
-    d.b64 = (double*)(base + o_b64);
-    d.cp64 = (double*)(base + o_cp64);
-    d.rd64 = (double*)(base + o_rd64);
-    d.wpad = (const double2*)(base + o_wpad);
+    d.starts = (int64_t*)o_starts;
+    d.wR = (double*)o_wR;
+    d.wL = (double*)o_wL;
+    d.rho = (double*)o_rho;
+    d.lam = (double*)o_lam;
+    d.a64 = (double*)o_a64;
+    d.b64 = (double*)o_b64;
+    d.cp64 = (double*)o_cp64;
+    d.rd64 = (double*)o_rd64;
+    d.wpad = (const double2*)o_wpad;
     d.wpad_rows = WP;
-    d.in64 = (double*)(base + o_in64);
-    d.u = (double*)(base + o_u);
-    d.v = (double*)(base + o_v);
-    d.a32 = (float*)(base + o_a32);
-    d.cp32 = (float*)(base + o_cp32);
-    d.rd32 = (float*)(base + o_rd32);
-    d.in32 = (float*)(base + o_in32);
+    d.in64 = (double*)o_in64;
+    d.u = (double*)o_u;
+    d.v = (double*)o_v;
+    d.a32 = (float*)o_a32;
+    d.cp32 = (float*)o_cp32;
+    d.rd32 = (float*)o_rd32;
+    d.in32 = (float*)o_in32;
+    return d;
+}
+
+template <typename T>
+void shift(T*& p, unsigned char* base) { p = (T*)(base + (size_t)p); }
+template <typename T>
+void shift(const T*& p, unsigned char* base) { p = (const T*)(base + (size_t)p); }
+
+void rebase(DevTables& d, void* mem) {
+    unsigned char* b = (unsigned char*)mem;
+    shift(d.starts, b); shift(d.wR, b); shift(d.wL, b); shift(d.rho, b); shift(d.lam, b);
+    shift(d.a64, b); shift(d.b64, b); shift(d.cp64, b); shift(d.rd64, b); shift(d.wpad, b);
+    shift(d.in64, b); shift(d.u, b); shift(d.v, b); shift(d.a32, b); shift(d.cp32, b);
+    shift(d.rd32, b); shift(d.in32, b);
+}
+
+int upload_image(const std::vector<unsigned char>& img, void** out) {
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, std::max<size_t>(img.size(), 256));
+    if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
+    if (e != hipSuccess) return TDS_EHIP;
+    if (hipMemcpy(mem, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        return TDS_EHIP;
+    }
+    *out = mem;
+    return TDS_OK;
+}
+
+int upload(tds_plan* h) {
+    if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
+    std::vector<unsigned char> img;
+    h->dev = append_image(h->host, rows_bucket(h->host.max_rows), img);
+    int rc = upload_image(img, &h->dev_mem);
+    if (rc) return rc;
+    rebase(h->dev, h->dev_mem);
     return TDS_OK;
 }
 
@@ -156,7 +188,7 @@ size_t f_elem(int32_t m) { return m == TDS_F64 ? 8 : 4; }
 size_t x_elem(int32_t m) { return m == TDS_F32 ? 4 : 8; }
 
 int check_common(tds_plan* h, int64_t N, int32_t mode) {
-    if (!h) return TDS_EINVAL;
+    if (!h || h->is_batch) return TDS_EINVAL;
     if (N < 0 || !valid_mode(mode)) return TDS_EINVAL;
     if ((N + kWG - 1) / kWG > 0x7fffffffLL) return TDS_EUNSUPPORTED;
     return TDS_OK;
@@ -354,7 +386,7 @@ int tdsolve_set_refinement(tds_handle h, int32_t passes) {
 }
 
 int tdsolve_info(tds_handle h, tds_info* info) {
-    if (!h || !info) return TDS_EINVAL;
+    if (!h || !info || h->is_batch) return TDS_EINVAL;
     info->M = h->host.M;
     info->P = h->host.P;
     info->max_block = h->host.max_rows;
@@ -386,6 +418,7 @@ int tdsolve_destroy(tds_handle h) {
     if (h->work) (void)hipFree(h->work);
     if (h->dev_mem) (void)hipFree(h->dev_mem);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->d_desc) (void)hipFree(h->d_desc);
     delete h;
     return TDS_OK;
 }
@@ -403,15 +436,102 @@ const char* tdsolve_strerror(int code) {
     }
 }
 
-int tdsolve_batch_prepare(int32_t, const double* const*, const double* const*, const int64_t*,
-                          const int32_t*, tds_handle* out) {
-    if (out) *out = nullptr;
-    return TDS_EUNSUPPORTED;
+int tdsolve_batch_prepare(int32_t K, const double* const* a, const double* const* b,
+                          const int64_t* M, const int32_t* P, tds_handle* out) {
+    if (!out) return TDS_EINVAL;
+    *out = nullptr;
+    if (K < 1 || !a || !b || !M) return TDS_EINVAL;
+    tds_plan* h = new (std::nothrow) tds_plan();
+    if (!h) return TDS_ENOMEM;
+    h->is_batch = true;
+    h->hosts.resize(K);
+    int32_t bucket = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        int rc = host_prepare(a[k], b[k], M[k], P ? P[k] : 0, h->hosts[k]);
+        if (rc) { delete h; return rc; }
+        const int32_t bk = rows_bucket(h->hosts[k].max_rows);
+        if (bk == 0 || bk > 64) { delete h; return TDS_EUNSUPPORTED; }   // blocks > 64 rows
+        bucket = std::max(bucket, bk);
+    }
+    h->bucket = bucket;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return TDS_EHIP; }
+    std::vector<unsigned char> img;
+    h->devs.resize(K);
+    for (int32_t k = 0; k < K; ++k) h->devs[k] = append_image(h->hosts[k], bucket, img);
+    int rc = upload_image(img, &h->dev_mem);
+    if (rc) { delete h; return rc; }
+    for (int32_t k = 0; k < K; ++k) rebase(h->devs[k], h->dev_mem);
+    *out = h;
+    return TDS_OK;
 }
 
-int tdsolve_batch_series(tds_handle, const void* const*, void* const*, const int64_t*, int32_t,
-                         void*) {
-    return TDS_EUNSUPPORTED;
+int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, const int64_t* N,
+                         int32_t mode, void* stream) {
+    if (!h || !h->is_batch || !F || !X || !N || !valid_mode(mode)) return TDS_EINVAL;
+    const int32_t K = (int32_t)h->devs.size();
+    // work buffer slices and work-item ranges of every matrix
+    std::vector<BatchDesc> desc(K);
+    size_t bytes = 0;
+    int64_t items = 0, scans = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        const DevTables& t = h->devs[k];
+        const int64_t n = N[k];
+        if (n < 0 || (n > 0 && (!F[k] || !X[k]))) return TDS_EINVAL;
+        if (n > 0 && F[k] == X[k] && f_elem(mode) != x_elem(mode)) return TDS_EINVAL;
+        BatchDesc& d = desc[k];
+        d.F = F[k];
+        d.X = X[k];
+        d.N = n;
+        d.T = t;
+        d.item0 = items;
+        d.scan0 = scans;
+        scan_shape(t.P, &d.per, &d.G);
+        const size_t nb = align256(sizeof(double) * (size_t)t.P * (size_t)n);
+        d.betaR = (double*)bytes;
+        d.betaL = (double*)(bytes + nb);
+        d.xsep = (double*)(bytes + 2 * nb);
+        bytes += 2 * nb + align256(sizeof(double) * (size_t)(t.P > 1 ? t.P - 1 : 1) * (size_t)n);
+        if (n > 0) {
+            items += (int64_t)t.P * ((n + kWG - 1) / kWG);
+            if (t.P > 1) scans += (n + 63) / 64;
+        }
+    }
+    if (items == 0) return TDS_OK;
+    if (items > 0x7fffffffLL || scans > 0x7fffffffLL) return TDS_EUNSUPPORTED;
+    int rc = ensure_work(h, std::max<size_t>(bytes, 256));
+    if (rc) return rc;
+    for (auto& d : desc) {
+        d.betaR = (double*)(general_of(h) + (size_t)d.betaR);
+        d.betaL = (double*)(general_of(h) + (size_t)d.betaL);
+        d.xsep = (double*)(general_of(h) + (size_t)d.xsep);
+    }
+    // descriptors go to the device only when they change, so that repeated
+    // calls on the same buffers (e.g. replays of a captured graph) carry no
+    // host-to-device copy
+    const bool same = desc.size() == h->desc.size() &&
+                      memcmp(desc.data(), h->desc.data(), sizeof(BatchDesc) * desc.size()) == 0;
+    if (!same) {
+        if (h->desc_cap < desc.size()) {
+            if (h->d_desc) {
+                if (hipDeviceSynchronize() != hipSuccess) return TDS_EHIP;
+                (void)hipFree(h->d_desc);
+                h->d_desc = nullptr;
+            }
+            if (hipMalloc(&h->d_desc, sizeof(BatchDesc) * desc.size()) != hipSuccess)
+                return TDS_ENOMEM;
+            h->desc_cap = desc.size();
+        }
+        // ordered after any queued work that still reads the old descriptors
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return TDS_EHIP;
+        if (hipMemcpy(h->d_desc, desc.data(), sizeof(BatchDesc) * desc.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return TDS_EHIP;
+        h->desc = desc;
+    }
+    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes,
+                     (hipStream_t)stream) != hipSuccess)
+        return TDS_EHIP;
+    return TDS_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,154 @@
+// HIP kernels for gfx950 (MI355X) outside the solve itself: residual
+// metrics of a computed solution and the reductions of the adjoint
+// (gradients with respect to the matrix coefficients).
+#include "tdsolve.h"
+#include "tds_internal.h"
+
+namespace tds {
+
+static inline dim3 grid2(int64_t N, int64_t y) {
+    return dim3((unsigned)((N + kWG - 1) / kWG), (unsigned)y, 1);
+}
+
+// --------------------------------------------------------------------------
+// Residual metrics: per (row chunk, RHS) partials, then a per-RHS finish.
+template <typename Fin, typename Xin>
+__global__ __launch_bounds__(kWG) void k_resid_part(const Fin* __restrict__ F,
+                                                    const Xin* __restrict__ X, int64_t N,
+                                                    int64_t M, const double* __restrict__ a64,
+                                                    const double* __restrict__ b64,
+                                                    double* __restrict__ part) {
+    const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (n >= N) return;
+    const int64_t lo = c * kReduceRowChunk;
+    const int64_t hi = (lo + kReduceRowChunk < M) ? lo + kReduceRowChunk : M;
+    double rmx = 0.0, r2 = 0.0, xmx = 0.0, fmx = 0.0, f2 = 0.0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const double x = (double)X[i * N + n];
+        double r = (double)F[i * N + n] - b64[i] * x;
+        if (i > 0) r -= a64[i - 1] * (double)X[(i - 1) * N + n];
+        if (i + 1 < M) r -= a64[i] * (double)X[(i + 1) * N + n];
+        const double f = (double)F[i * N + n];
+        rmx = fmax(rmx, fabs(r));
+        r2 += r * r;
+        xmx = fmax(xmx, fabs(x));
+        fmx = fmax(fmx, fabs(f));
+        f2 += f * f;
+    }
+    double* p = part + (c * 5) * N + n;
+    p[0] = rmx;
+    p[N] = r2;
+    p[2 * N] = xmx;
+    p[3 * N] = fmx;
+    p[4 * N] = f2;
+}
+
+__global__ __launch_bounds__(kWG) void k_resid_finish(const double* __restrict__ part, int64_t N,
+                                                      int64_t chunks, double normA,
+                                                      double* __restrict__ out) {
+    const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (n >= N) return;
+    double rmx = 0.0, r2 = 0.0, xmx = 0.0, fmx = 0.0, f2 = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) {
+        const double* p = part + (c * 5) * N + n;
+        rmx = fmax(rmx, p[0]);
+        r2 += p[N];
+        xmx = fmax(xmx, p[2 * N]);
+        fmx = fmax(fmx, p[3 * N]);
+        f2 += p[4 * N];
+    }
+    const double den = normA * xmx + fmx;
+    out[n] = den > 0.0 ? rmx / den : 0.0;
+    out[N + n] = f2 > 0.0 ? sqrt(r2) / sqrt(f2) : sqrt(r2);
+}
+
+// --------------------------------------------------------------------------
+// Adjoint reductions over the series: one workgroup per row i, a fixed
+// strided order per lane and a fixed LDS tree, so results are bitwise
+// reproducible (no floating-point atomics).
+template <typename Xin, typename Gin>
+__global__ __launch_bounds__(kWG) void k_adjoint_reduce(const Xin* __restrict__ X,
+                                                        const Gin* __restrict__ gF, int64_t N,
+                                                        int64_t M, double* __restrict__ ga,
+                                                        double* __restrict__ gb) {
+    __shared__ double sa[kWG], sb[kWG];
+    const int64_t i = blockIdx.x;
+    double accb = 0.0, acca = 0.0;
+    const bool has_next = (i + 1 < M);
+    for (int64_t n = threadIdx.x; n < N; n += kWG) {
+        const double x = (double)X[i * N + n];
+        const double g = (double)gF[i * N + n];
+        accb = fma(g, x, accb);
+        if (has_next) {
+            const double x1 = (double)X[(i + 1) * N + n];
+            const double g1 = (double)gF[(i + 1) * N + n];
+            acca = fma(g, x1, acca);
+            acca = fma(g1, x, acca);
+        }
+    }
+    sa[threadIdx.x] = acca;
+    sb[threadIdx.x] = accb;
+    __syncthreads();
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (gb) gb[i] = -sb[0];
+        if (ga && has_next) ga[i] = -sa[0];
+    }
+}
+
+// ==========================================================================
+// launchers
+hipError_t launch_residual(const DevTables& t, const void* F, const void* X, int64_t N,
+                           int mode, double normA, double* part, double* out, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    const int64_t chunks = (t.M + kReduceRowChunk - 1) / kReduceRowChunk;
+    dim3 g = grid2(N, chunks);
+    switch (mode) {
+        case TDS_F64:
+            hipLaunchKernelGGL((k_resid_part<double, double>), g, dim3(kWG), 0, s,
+                               (const double*)F, (const double*)X, N, t.M, t.a64, t.b64, part);
+            break;
+        case TDS_F32:
+            hipLaunchKernelGGL((k_resid_part<float, float>), g, dim3(kWG), 0, s,
+                               (const float*)F, (const float*)X, N, t.M, t.a64, t.b64, part);
+            break;
+        default:
+            hipLaunchKernelGGL((k_resid_part<float, double>), g, dim3(kWG), 0, s,
+                               (const float*)F, (const double*)X, N, t.M, t.a64, t.b64, part);
+            break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resid_finish, grid2(N, 1), dim3(kWG), 0, s, part, N, chunks, normA,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(const DevTables& t, const void* X, const void* gF, bool f32x,
+                                 bool f32g, int64_t N, double* /*part*/, double* ga,
+                                 double* gb, hipStream_t s) {
+    if (N == 0 || (!ga && !gb)) return hipSuccess;
+    dim3 g((unsigned)t.M, 1, 1);
+    if (!f32x && !f32g)
+        hipLaunchKernelGGL((k_adjoint_reduce<double, double>), g, dim3(kWG), 0, s,
+                           (const double*)X, (const double*)gF, N, t.M, ga, gb);
+    else if (!f32x && f32g)
+        hipLaunchKernelGGL((k_adjoint_reduce<double, float>), g, dim3(kWG), 0, s,
+                           (const double*)X, (const float*)gF, N, t.M, ga, gb);
+    else if (f32x && f32g)
+        hipLaunchKernelGGL((k_adjoint_reduce<float, float>), g, dim3(kWG), 0, s,
+                           (const float*)X, (const float*)gF, N, t.M, ga, gb);
+    else
+        hipLaunchKernelGGL((k_adjoint_reduce<float, double>), g, dim3(kWG), 0, s,
+                           (const float*)X, (const double*)gF, N, t.M, ga, gb);
+    return hipGetLastError();
+}
+
+}  // namespace tds

@@ -74,6 +74,36 @@ hipError_t launch_iface(const DevTables& t, const double* betaR,
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         int mode, int passes, const double* xsep,
                         hipStream_t s);
+
+// register-sweep row bucket (32, 64, 128) of a largest block size, 0 if the
+// streaming sweep is needed
+int32_t rows_bucket(int32_t max_rows);
+// shape of the two-level interface scan: blocks per group, groups (<= 16)
+void scan_shape(int32_t P, int32_t* per, int32_t* G);
+
+// One matrix of a batch: its tables, its series and its slices of the work
+// buffer, and where its work items start in the batch launches (item0: beta
+// and sweep items, P * ceil(N/256) of them; scan0: interface workgroups,
+// ceil(N/64) of them).
+struct BatchDesc {
+    const void* F;
+    void* X;
+    int64_t N;
+    DevTables T;
+    double* betaR;
+    double* betaL;
+    double* xsep;
+    int64_t item0;
+    int64_t scan0;
+    int32_t per;
+    int32_t G;
+};
+
+// The three steps for all matrices of a batch: one launch each.  `bucket`
+// is the common register-sweep row bucket (32 or 64).
+hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items,
+                        int64_t scans, int32_t bucket, int mode, int passes,
+                        hipStream_t s);
 hipError_t launch_residual(const DevTables& t, const void* F, const void* X,
                            int64_t N, int mode, double normA, double* part,
                            double* out, hipStream_t s);

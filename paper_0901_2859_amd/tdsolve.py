@@ -246,6 +246,66 @@ class Plan:
             pass
 
 
+class BatchPlan:
+    """K independent matrices of uneven sizes prepared together; every
+    series solve of the batch is one launch per step of the method for all
+    K matrices (tdsolve_batch_series)."""
+
+    def __init__(self, a_list, b_list, P_list=None):
+        L = lib()
+        K = len(b_list)
+        if K < 1 or len(a_list) != K:
+            raise ValueError("need K >= 1 matrices with matching a and b")
+        self._bs = [_host_f64(b) for b in b_list]
+        self._as = [(_host_f64(a) if len(b) > 1 else np.zeros(1)) for a, b in zip(a_list, self._bs)]
+        self.M = [int(b.shape[0]) for b in self._bs]
+        Ms = np.array(self.M, dtype=np.int64)
+        Ps = np.array(P_list if P_list is not None else [0] * K, dtype=np.int32)
+        ap = (ctypes.c_void_p * K)(*[x.ctypes.data for x in self._as])
+        bp = (ctypes.c_void_p * K)(*[x.ctypes.data for x in self._bs])
+        h = ctypes.c_void_p()
+        _check(L.tdsolve_batch_prepare(K, ap, bp, _ptr(Ms), _ptr(Ps), ctypes.byref(h)),
+               "tdsolve_batch_prepare")
+        self._h = h
+        self.K = K
+
+    def solve(self, F_list, X_list=None, mode="f32_refined", stream=None):
+        import torch
+        m = mode_id(mode)
+        if len(F_list) != self.K:
+            raise ValueError("one right-hand-side array per matrix")
+        if X_list is None:
+            X_list = [torch.empty((self.M[k], F_list[k].shape[1]),
+                                  dtype=getattr(torch, _X_DTYPE[m]), device=F_list[k].device)
+                      for k in range(self.K)]
+        Ns = np.zeros(self.K, dtype=np.int64)
+        for k in range(self.K):
+            F, X = F_list[k], X_list[k]
+            for t_, name, dt in ((F, "F", _F_DTYPE[m]), (X, "X", _X_DTYPE[m])):
+                if not t_.is_cuda or t_.dtype != getattr(torch, dt) or t_.dim() != 2 \
+                        or t_.shape[0] != self.M[k] or not t_.is_contiguous():
+                    raise ValueError(f"{name}[{k}] must be a contiguous ({self.M[k]}, N) {dt} device tensor")
+            if X.shape[1] != F.shape[1]:
+                raise ValueError(f"X[{k}] and F[{k}] differ in N")
+            Ns[k] = F.shape[1]
+        Fp = (ctypes.c_void_p * self.K)(*[F.data_ptr() for F in F_list])
+        Xp = (ctypes.c_void_p * self.K)(*[X.data_ptr() for X in X_list])
+        _check(lib().tdsolve_batch_series(self._h, Fp, Xp, _ptr(Ns), m, _stream_ptr(stream)),
+               "tdsolve_batch_series")
+        return X_list
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tdsolve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _autograd_fn():
     import torch
 

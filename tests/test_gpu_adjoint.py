@@ -1,0 +1,125 @@
+"""GPU adjoint: gradients of a loss L(X), X = A(a, b)^{-1} F, through the
+C ABI's tdsolve_backward and the autograd binding, against the CPU oracle's
+FP64 gradient (itself pinned to central finite differences in the CPU
+suite) and against finite differences of the GPU solve.
+
+Tolerances: the FP64 modes reproduce the oracle's reductions up to rounding
+order, so ga, gb, gF agree to 1e-11 relative (normwise).  In the FP32-storage
+modes gF is rounded to FP32 on output (1e-6 relative) while ga and gb are
+reduced in FP64 from an FP64 adjoint solve (1e-9 relative).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_0901_2859_amd import tdsolve as t  # noqa: E402
+from paper_0901_2859_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _nrel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+@pytest.mark.parametrize("M,N,P", [(300, 100, 10), (2048, 257, 32), (64, 1, 1), (9, 600, 4)])
+def test_backward_f64_matches_oracle(M, N, P):
+    print(f"case M={M} N={N} P={P}", flush=True)
+    w = wl.random_dominant(seed=M + N, M=M, N=N)
+    a, b, F = w["a"], w["b"], w["F"]
+    W = np.random.default_rng(M).uniform(-1, 1, size=(M, N))
+    X = oracle.thomas(a, b, F)
+    gF_or, ga_or, gb_or = oracle.grad(a, b, X, W)
+    plan = t.Plan(a, b, P)
+    Xd = plan.solve(torch.from_numpy(F).to(DEV), mode="f64")
+    gF, ga, gb = plan.backward(Xd, torch.from_numpy(W).to(DEV), mode="f64")
+    assert _nrel(gF.cpu().numpy(), gF_or) <= 1e-11
+    assert _nrel(gb.cpu().numpy(), gb_or) <= 1e-11
+    if M > 1:
+        assert _nrel(ga.cpu().numpy(), ga_or) <= 1e-11
+
+
+def test_gradient_case_autograd_refined():
+    # differentiation workload: M=2048, N=1024, b = 3 + U[0,1],
+    # a ~ U[-1,-0.5], FP32 storage, loss = sum(W * X)
+    w = wl.gradient_case()
+    a, b, F32, W = w["a"], w["b"], w["F"], w["W"]
+    Fw = F32.astype(np.float64)
+    X_or = oracle.thomas(a, b, Fw)
+    gF_or, ga_or, gb_or = oracle.grad(a, b, X_or, W)
+
+    Ft = torch.from_numpy(F32).to(DEV).requires_grad_(True)
+    at = torch.from_numpy(a).to(DEV).requires_grad_(True)
+    bt = torch.from_numpy(b).to(DEV).requires_grad_(True)
+    Wt = torch.from_numpy(W).to(DEV)
+    X = t.tdsolve(Ft, at, bt, w["P"], "f32_refined")
+    loss = (Wt * X).sum()
+    loss.backward()
+    assert Ft.grad.dtype == torch.float32
+    assert _nrel(X.detach().cpu().numpy(), X_or) <= 1e-12
+    assert _nrel(Ft.grad.cpu().numpy(), gF_or) <= 1e-6
+    assert _nrel(at.grad.cpu().numpy(), ga_or) <= 1e-9
+    assert _nrel(bt.grad.cpu().numpy(), gb_or) <= 1e-9
+
+
+def test_gradient_finite_differences_through_gpu():
+    # central differences (h = 1e-6) of the GPU solve itself, FP64 mode
+    rng = np.random.default_rng(8)
+    M, N, P = 24, 5, 4
+    w = wl.random_dominant(seed=77, M=M, N=N)
+    a, b, F = w["a"], w["b"], w["F"]
+    W = rng.uniform(-1, 1, size=(M, N))
+    Wt = torch.from_numpy(W).to(DEV)
+
+    def loss(a_, b_, F_):
+        plan = t.Plan(a_, b_, P)
+        X = plan.solve(torch.from_numpy(F_).to(DEV), mode="f64")
+        return float((Wt * X).sum())
+
+    at = torch.from_numpy(a).to(DEV).requires_grad_(True)
+    bt = torch.from_numpy(b).to(DEV).requires_grad_(True)
+    Ft = torch.from_numpy(F).to(DEV).requires_grad_(True)
+    (Wt * t.tdsolve(Ft, at, bt, P, "f64")).sum().backward()
+    h = 1e-6
+    for i in range(M - 1):
+        d = np.zeros(M - 1); d[i] = h
+        fd = (loss(a + d, b, F) - loss(a - d, b, F)) / (2 * h)
+        assert abs(fd - at.grad[i].item()) <= 1e-6 * max(1.0, abs(fd))
+    for i in range(M):
+        d = np.zeros(M); d[i] = h
+        fd = (loss(a, b + d, F) - loss(a, b - d, F)) / (2 * h)
+        assert abs(fd - bt.grad[i].item()) <= 1e-6 * max(1.0, abs(fd))
+    for (i, n) in [(0, 0), (11, 3), (M - 1, N - 1)]:
+        d = np.zeros((M, N)); d[i, n] = h
+        fd = (loss(a, b, F + d) - loss(a, b, F - d)) / (2 * h)
+        assert abs(fd - Ft.grad[i, n].item()) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_backward_bitwise_reproducible():
+    w = wl.random_dominant(seed=5, M=1000, N=700, dtype=np.float32)
+    a, b, F = w["a"], w["b"], w["F"]
+    plan = t.Plan(a, b, 16)
+    X = plan.solve(torch.from_numpy(F).to(DEV), mode="f32_refined")
+    gX = torch.ones_like(X)
+    g1 = [v.clone() for v in plan.backward(X, gX, mode="f32_refined")]
+    g2 = plan.backward(X, gX, mode="f32_refined")
+    for u, v in zip(g1, g2):
+        assert torch.equal(u, v)
+
+
+def test_backward_fp32_mode():
+    w = wl.random_dominant(seed=6, M=500, N=300, dtype=np.float32)
+    a, b, F = w["a"], w["b"], w["F"]
+    W = np.random.default_rng(1).uniform(-1, 1, size=F.shape)
+    X_or = oracle.thomas(a, b, F.astype(np.float64))
+    gF_or, ga_or, gb_or = oracle.grad(a, b, X_or, W)
+    plan = t.Plan(a, b, 10)
+    X = plan.solve(torch.from_numpy(F).to(DEV), mode="f32")
+    gF, ga, gb = plan.backward(X, torch.from_numpy(W.astype(np.float32)).to(DEV), mode="f32")
+    assert _nrel(gF.cpu().numpy(), gF_or) <= 1e-5
+    assert _nrel(ga.cpu().numpy(), ga_or) <= 1e-4
+    assert _nrel(gb.cpu().numpy(), gb_or) <= 1e-4

@@ -1,0 +1,110 @@
+"""GPU parity of the uneven batch (many matrices of different sizes and
+series lengths solved by one launch per step) against the CPU oracle, and
+of its replays from a captured HIP graph.
+
+Tolerance: as in the single-matrix parity tests, per right-hand side
+e_n <= 1e-11 + 8 (t + 2P) u cond_n with cond_n = max_k sum_i |G_k(i)||F_i,n|
+/ |X_or,n|_inf (rows G_k of A^{-1} at the interface rows); the batch
+matrices are shifted Poisson matrices with b_i = 2 + c_i, c_i >= 0.01.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import method  # noqa: E402
+from paper_0901_2859_amd import tdsolve as t  # noqa: E402
+from paper_0901_2859_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _check(a, b, F64, X, P):
+    ref = oracle.thomas(a, b, F64)
+    e = np.max(np.abs(X - ref), axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
+    if P > 1:
+        tt, s = method.partition(len(b), P)
+        G = method.green_rows(a, b, s[1:P])
+        cond = (np.abs(G).T @ np.abs(F64)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
+        tol = 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+    else:
+        tol = np.full(F64.shape[1], 1e-11)
+    bad = np.nonzero(e > tol)[0]
+    assert bad.size == 0, (bad[:5], e[bad[:5]], tol[bad[:5]])
+
+
+@pytest.mark.parametrize("mode", ["f32_refined", "f32_wide", "f64"])
+def test_uneven_batch_parity(mode):
+    w = wl.uneven_batch(seed=3, K=24, M_lo=128, M_hi=3000, N_hi=700)
+    items = w["items"]
+    print(f"batch K={len(items)} mode={mode}", flush=True)
+    bp = t.BatchPlan([it["a"] for it in items], [it["b"] for it in items])
+    Fs = []
+    for it in items:
+        F = torch.from_numpy(it["F"]).to(DEV)
+        Fs.append(F.double() if mode == "f64" else F)
+    Xs = bp.solve(Fs, mode=mode)
+    torch.cuda.synchronize()
+    plans = [t.Plan(it["a"], it["b"], 0) for it in items]
+    for k, it in enumerate(items):
+        _check(it["a"], it["b"], it["F"].astype(np.float64), Xs[k].cpu().numpy(), plans[k].P)
+
+
+def test_batch_ragged_shapes_and_empty_series():
+    rng = np.random.default_rng(4)
+    Ms = [2, 5, 64, 65, 129, 1000, 300]
+    Ns = [3, 0, 1, 257, 513, 40, 2]
+    a_l, b_l, F_l = [], [], []
+    for M, N in zip(Ms, Ns):
+        a = rng.uniform(-1, -0.5, size=M - 1)
+        b = 2.2 + rng.uniform(0, 1, size=M)
+        a_l.append(a); b_l.append(b)
+        F_l.append(rng.uniform(-1, 1, size=(M, N)).astype(np.float32))
+    P_l = [1, 2, 0, 0, 4, 0, 5]
+    bp = t.BatchPlan(a_l, b_l, P_l)
+    Xs = bp.solve([torch.from_numpy(F).to(DEV) for F in F_l], mode="f32_refined")
+    for k in range(len(Ms)):
+        if Ns[k] == 0:
+            continue
+        P = P_l[k] or t.default_blocks(Ms[k])
+        _check(a_l[k], b_l[k], F_l[k].astype(np.float64), Xs[k].cpu().numpy(), P)
+
+
+def test_batch_matches_single_plans_bitwise():
+    w = wl.uneven_batch(seed=11, K=6, M_lo=128, M_hi=1500, N_hi=400)
+    items = w["items"]
+    bp = t.BatchPlan([it["a"] for it in items], [it["b"] for it in items])
+    Fs = [torch.from_numpy(it["F"]).to(DEV) for it in items]
+    Xs = bp.solve(Fs, mode="f32_refined")
+    for k, it in enumerate(items):
+        X1 = t.Plan(it["a"], it["b"], 0).solve(Fs[k], mode="f32_refined")
+        assert torch.equal(X1, Xs[k])
+
+
+def test_batch_graph_replays():
+    # capture the batch solve once, replay it several times with eager work
+    # and synchronizations in between; every replay must equal the eager solve
+    w = wl.uneven_batch(seed=12, K=8, M_lo=128, M_hi=2000, N_hi=500)
+    items = w["items"]
+    bp = t.BatchPlan([it["a"] for it in items], [it["b"] for it in items])
+    Fs = [torch.from_numpy(it["F"]).to(DEV) for it in items]
+    Xs = [torch.empty((it["M"], it["N"]), dtype=torch.float64, device=DEV) for it in items]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        bp.solve(Fs, Xs, mode="f32_refined")          # eager: uploads descriptors
+    torch.cuda.synchronize()
+    ref = [X.clone() for X in Xs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bp.solve(Fs, Xs, mode="f32_refined")
+    for rep in range(4):
+        for X in Xs:
+            X.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for X, R in zip(Xs, ref):
+            assert torch.equal(X, R), rep
+        _ = (Fs[0] * 2).sum().item()                   # eager work between replays
