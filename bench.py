@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
+    p.add_argument("--path", default="auto", choices=["auto", "three", "single"],
+                   help="launch structure: single pass, three kernels, or automatic")
     p.add_argument("--sets", type=int, default=0,
                    help="buffer sets rotated across steps (0: enough to exceed 512 MB)")
     p.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison runs")
@@ -95,6 +97,7 @@ def main():
     a, b, F32 = w["a"], w["b"], w["F"]
     dev = torch.device("cuda:0")
     plan = t.Plan(a, b, P)
+    plan.set_path(args.path)
 
     f_bytes = {"f32_refined": 4, "f32_wide": 4, "f32": 4, "f64": 8}
     x_bytes = {"f32_refined": 8, "f32_wide": 8, "f32": 4, "f64": 8}
@@ -113,6 +116,7 @@ def main():
     def run(mode, steps, warmup):
         Fs, Xs = make_sets(mode)
         r = time_mode(plan, Fs, Xs, mode, steps, warmup, torch)
+        plan.check()
         eta, r2 = plan.residual(Fs[0], Xs[0], mode=mode)
         torch.cuda.synchronize()
         r["eta_max"] = float(eta.max())
@@ -132,9 +136,10 @@ def main():
     sweep_bytes = M * N * (f_bytes[args.mode] + x_bytes[args.mode]) + 2 * (P - 1) * N * 8
     ms_sweep = main_r["ms_sweep"]
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
+    fused = main_r["ms_beta"] + main_r["ms_iface"] < 1e-4
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep_reg", "bytes_per_launch": sweep_bytes,
+                "kernel": "k_fused" if fused else "k_sweep_reg", "bytes_per_launch": sweep_bytes,
                 "ms_per_launch": round(ms_sweep, 5)}
 
     compare = {}

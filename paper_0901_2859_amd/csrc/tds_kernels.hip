@@ -23,6 +23,8 @@
 // kernels index items by their 2-D grid, the batch kernels (many matrices of
 // uneven sizes in one launch per step) find their matrix and item in a
 // descriptor table.
+#include <type_traits>
+
 #include "tdsolve.h"
 #include "tds_internal.h"
 
@@ -38,6 +40,18 @@ __device__ __forceinline__ cptr<T> cst(const T* p) {
     return (cptr<T>)p;
 }
 
+// element at a wave-uniform base plus an unsigned 32-bit byte offset: the
+// form of the global scalar-base address mode (64-bit base in SGPRs, 32-bit
+// offset in one VGPR), which saves a 64-bit VGPR address per row
+template <typename T>
+__device__ __forceinline__ T& at_off(T* base, uint32_t byte_off) {
+    return *(T*)((char*)base + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ const T& at_off(const T* base, uint32_t byte_off) {
+    return *(const T*)((const char*)base + byte_off);
+}
+
 // ==========================================================================
 // beta weights (eq. beta_symn).  Item (tile, j): block j of rows x 256
 // consecutive right-hand sides, one per lane.  All rows of the block are
@@ -51,17 +65,25 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
                                           double* __restrict__ betaL) {
     const int64_t lo = cst(T.starts)[j];
     const int t = (int)(cst(T.starts)[j + 1] - lo);
-    const int64_t n = tile * kWG + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t n = tile * kWG + lane;
     if (n >= N) return;
-    const Fin* f = F + lo * N + n;
+    // wave-uniform row bases plus one 32-bit lane offset: the loads use the
+    // scalar-base addressing form instead of a 64-bit address per row
+    const Fin* fb = F + lo * N + tile * kWG;
+    const Fin* f = fb + lane;
     double bR = 0.0, bL = 0.0;
     if constexpr (TMAX > 0) {
         const cptr<double2> w = cst(T.wpad + (int64_t)j * TMAX);
         Fin v[TMAX];
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r) v[r] = f[(int64_t)(r < t ? r : t - 1) * N];
+        for (int r = 0; r < TMAX; ++r)
+            v[r] = at_off(fb + (int64_t)(r < t ? r : t - 1) * N, (uint32_t)lane * sizeof(Fin));
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
+            // convert each value next to its use: converting all of them as
+            // they arrive would double the registers the loads occupy
+            if ((r & 7) == 0) __builtin_amdgcn_sched_barrier(0);
             const double cR = w[r].x, cL = w[r].y;
             bR = fma(cR, (double)v[r], bR);
             bL = fma(cL, (double)v[r], bL);
@@ -227,8 +249,19 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
 // finite, and they never feed back into real rows because the last real
 // row's elimination factor and block-interior coupling are zero.  They are
 // not stored.
+// the block's interior rows of F for one lane (rows past cnt re-read the
+// last row)
+// (fb: wave-uniform base of the block's first interior row, lane: the
+// lane's offset; the loads then take the scalar-base addressing form)
+template <int TMAX, typename Fin>
+__device__ __forceinline__ void sweep_load(const Fin* __restrict__ fb, int lane, int64_t N,
+                                           int cnt, Fin (&f)[TMAX]) {
+#pragma unroll
+    for (int r = 0; r < TMAX; ++r) f[r] = (fb + (int64_t)(r < cnt ? r : cnt - 1) * N)[lane];
+}
+
 template <int TMAX, typename Fin, typename Xout, int KIND>
-__device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __restrict__ xp,
+__device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restrict__ xb, int lane,
                                            int64_t N, int cnt, double cl, double xl, double cr,
                                            double xr, const DevTables& T, int64_t i0,
                                            float* __restrict__ my_f, int passes) {
@@ -236,10 +269,6 @@ __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __r
     const cptr<double> cp64 = cst(T.cp64 + i0), rd64 = cst(T.rd64 + i0);
     const cptr<double> uu = cst(T.u + i0), vv = cst(T.v + i0);
     const cptr<float> a32 = cst(T.a32 + i0), cp32 = cst(T.cp32 + i0), rd32 = cst(T.rd32 + i0);
-
-    Fin f[TMAX];
-#pragma unroll
-    for (int r = 0; r < TMAX; ++r) f[r] = fp[(int64_t)(r < cnt ? r : cnt - 1) * N];
 
     if constexpr (KIND == kSweep64 || KIND == kSweep32) {
         // one pass: the known boundary values are moved to the right-hand
@@ -260,12 +289,10 @@ __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __r
                 d[r] = (g(r) - sub * prev) * rd64[r];
             }
             double x = 0.0;
-            Xout* q = xp + (int64_t)(TMAX - 1) * N;
 #pragma unroll
             for (int r = TMAX - 1; r >= 0; --r) {
                 x = d[r] - cp64[r] * x;
-                if (r < cnt) *q = (Xout)x;
-                q -= N;
+                if (r < cnt) (xb + (int64_t)r * N)[lane] = (Xout)x;
             }
         } else {
             float w[TMAX];
@@ -276,12 +303,10 @@ __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __r
                 w[r] = ((float)g(r) - sub * prev) * rd32[r];
             }
             float x = 0.0f;
-            Xout* q = xp + (int64_t)(TMAX - 1) * N;
 #pragma unroll
             for (int r = TMAX - 1; r >= 0; --r) {
                 x = w[r] - cp32[r] * x;
-                if (r < cnt) *q = (Xout)x;
-                q -= N;
+                if (r < cnt) (xb + (int64_t)r * N)[lane] = (Xout)x;
             }
         }
     } else {
@@ -343,12 +368,9 @@ __device__ __forceinline__ void sweep_body(const Fin* __restrict__ fp, Xout* __r
                 x[r] += (double)dl;
             }
         }
-        Xout* q = xp;
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            if (r < cnt) *q = (Xout)fma(xr, vv[r], fma(xl, uu[r], x[r]));
-            q += N;
-        }
+        for (int r = 0; r < TMAX; ++r)
+            if (r < cnt) (xb + (int64_t)r * N)[lane] = (Xout)fma(xr, vv[r], fma(xl, uu[r], x[r]));
     }
 }
 
@@ -368,8 +390,11 @@ __device__ __forceinline__ void sweep_item(const DevTables& T, const Fin* __rest
     const double cl = (j > 0) ? cst(T.a64)[i0 - 1] : 0.0;         // A[i0][i0-1]
     const double cr = (j < P - 1) ? cst(T.a64)[seg_hi - 1] : 0.0; // A[i1][i1+1]
     if (j > 0) X[seg_lo * N + n] = (Xout)xl;
-    sweep_body<TMAX, Fin, Xout, KIND>(F + i0 * N + n, X + i0 * N + n, N, cnt, cl, xl, cr, xr, T,
-                                      i0, s_f + threadIdx.x, passes);
+    Fin f[TMAX];
+    const int lane = threadIdx.x;
+    sweep_load<TMAX, Fin>(F + i0 * N + tile * kWG, lane, N, cnt, f);
+    sweep_body<TMAX, Fin, Xout, KIND>(f, X + i0 * N + tile * kWG, lane, N, cnt, cl, xl, cr, xr, T,
+                                      i0, s_f + lane, passes);
 }
 
 // Block sweep for blocks longer than the register path holds: the forward
@@ -520,6 +545,199 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 }
 
 // ==========================================================================
+// Single-pass solve: beta, interface step and block sweep in one launch.
+//
+// Every workgroup owns one item (RHS tile, block j), taken from a ticket
+// counter in tile-major order, so the P blocks of a tile are dispatched
+// together.  It loads the block's rows of F once (kept in registers), forms
+// beta^R_j, beta^L_j, publishes them and counts itself in at its tile.  The
+// last of the tile's P workgroups to arrive runs the tile's interface step
+// (the two recurrences, serially per right-hand side) and raises the tile's
+// ready word to this launch's generation; the others wait for it, then all
+// sweep their block from the rows still in registers and write X.  F is read
+// from memory once.
+//
+// Progress: a workgroup only waits for tickets of its own tile, tickets are
+// taken in order, and every taken ticket publishes before waiting; so as long
+// as P workgroups fit on the device at once the tile's last ticket is always
+// taken and the wait ends.  The host only uses this kernel when P is at most
+// half of the resident capacity; the wait is also bounded (status flag).
+//
+// Control words (zeroed once; every launch leaves them ready for the next):
+//   sync[0] ticket counter, sync[1] finished workgroups, sync[2] generation of
+//   the last completed launch, sync[4 + tile] arrivals per tile,
+//   sync[4 + cap + tile] ready generation per tile, where cap is the tile
+//   capacity of the control area (fixed for its lifetime, so the positions
+//   do not move when N changes between launches).
+// Lanes past N compute on column N-1 and store the same values as its own
+// lane (plain stores of identical values), so the loads and the sweep need
+// no masking; only the in-place interface scan is restricted to live lanes.
+constexpr unsigned kSpinLimit = 1u << 20;
+
+// Cross-workgroup data of the single pass moves with device-coherent
+// (relaxed, agent-scope) loads and stores, which bypass the per-XCD L2
+// instead of needing whole-cache write-back / invalidate fences; ordering
+// comes from waiting for the stores' completion before the counter update
+// and from the control dependence on the counter / ready word.
+__device__ __forceinline__ void st_dev(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// wait until this wavefront's stores are complete
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// CH interface values per lane are loaded per round trip
+template <int CH>
+__device__ __forceinline__ void tile_scan(const DevTables& T, int64_t N, int64_t n,
+                                          const double* betaR, const double* betaL,
+                                          double* xsep) {
+    const int32_t P = T.P;
+    const cptr<double> rho = cst(T.rho), lam = cst(T.lam);
+    double SR = 0.0;
+    for (int32_t k0 = 0; k0 <= P - 2; k0 += CH) {
+        double bv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (k0 + u <= P - 2) bv[u] = ld_dev(betaR + (int64_t)(k0 + u) * N + n);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int32_t k = k0 + u;
+            if (k <= P - 2) {
+                SR = (k == 0) ? bv[u] : fma(rho[k], SR, bv[u]);
+                st_dev(xsep + (int64_t)k * N + n, SR);              // S^R_{k+1}
+            }
+        }
+    }
+    double SL = 0.0;
+    for (int32_t k1 = P - 1; k1 >= 1; k1 -= CH) {
+        double bv[CH], sr[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int32_t k = k1 - u;
+            if (k >= 1) {
+                bv[u] = ld_dev(betaL + (int64_t)k * N + n);
+                sr[u] = ld_dev(xsep + (int64_t)(k - 1) * N + n);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int32_t k = k1 - u;
+            if (k >= 1) {
+                SL = (k == P - 1) ? bv[u] : fma(lam[k], SL, bv[u]);
+                st_dev(xsep + (int64_t)(k - 1) * N + n, sr[u] + SL);   // x(s_k)
+            }
+        }
+    }
+}
+
+template <int TMAX, typename Fin, typename Xout, int KIND>
+__global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_fused(
+    DevTables T, const Fin* __restrict__ F, Xout* __restrict__ X, int64_t N, int64_t tiles,
+    double* betaR, double* betaL, double* xsep, unsigned* sync, int64_t cap, unsigned* status,
+    int passes) {
+    __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
+    __shared__ unsigned s_item, s_gen, s_last;
+    const int32_t P = T.P;
+    if (threadIdx.x == 0) {
+        s_item = atomicAdd(&sync[0], 1u);
+        s_gen = __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int64_t item = s_item;
+    const unsigned gen = s_gen + 1u;
+    const int64_t tile = item / P;
+    const int32_t j = (int32_t)(item - tile * P);
+    unsigned* arrive = sync + 4;
+    unsigned* ready = sync + 4 + cap;
+
+    const int64_t seg_lo = cst(T.starts)[j], seg_hi = cst(T.starts)[j + 1];
+    const int64_t i0 = (j == 0) ? seg_lo : seg_lo + 1;
+    const int cnt = (int)(seg_hi - i0);
+    const int64_t n0 = tile * kWG + threadIdx.x;
+    const int64_t n = n0 < N ? n0 : N - 1;
+    const int lane = (int)(n - tile * kWG);
+
+    // the block's rows of F, once
+    Fin f[TMAX];
+    sweep_load<TMAX, Fin>(F + i0 * N + tile * kWG, lane, N, cnt, f);
+    const double fs = (j > 0) ? (double)F[seg_lo * N + n] : 0.0;
+
+    // beta weights of the segment (eq. beta_symn)
+    {
+        const cptr<double2> w = cst(T.wint + (int64_t)j * TMAX);
+        double bR = cst(T.wsep)[j].x * fs, bL = cst(T.wsep)[j].y * fs;
+#pragma unroll
+        for (int r = 0; r < TMAX; ++r) {
+            const double wr = w[r].x, wl = w[r].y;
+            bR = fma(wr, (double)f[r], bR);
+            bL = fma(wl, (double)f[r], bL);
+        }
+        if (j < P - 1) st_dev(betaR + (int64_t)j * N + n, bR);
+        if (j > 0) st_dev(betaL + (int64_t)j * N + n, bL);
+    }
+    stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(&arrive[tile], 1u);
+        s_last = (prev == (unsigned)(P - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last) {
+        // interface step of the tile (Theorem 2); only live lanes: the
+        // backward pass updates xsep in place, which a duplicate lane in
+        // another wavefront would apply twice
+        // (the refined sweep needs more registers anyway, so its scan can
+        // keep twice as many values in flight)
+        if (n0 < N) tile_scan<KIND == kSweepRefined ? 32 : 16>(T, N, n, betaR, betaL, xsep);
+        stores_done();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            arrive[tile] = 0u;
+            __hip_atomic_store(&ready[tile], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        if (threadIdx.x == 0) {
+            // poll with relaxed device-scope loads (no cache invalidation)
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ready[tile], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                   gen) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(status, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __syncthreads();
+    }
+
+    // block sweep with the interface values known (Lemma 1)
+    const double xl = (j > 0) ? ld_dev(xsep + (int64_t)(j - 1) * N + n) : 0.0;
+    const double xr = (j < P - 1) ? ld_dev(xsep + (int64_t)j * N + n) : 0.0;
+    const double cl = (j > 0) ? cst(T.a64)[i0 - 1] : 0.0;
+    const double cr = (j < P - 1) ? cst(T.a64)[seg_hi - 1] : 0.0;
+    if (j > 0) X[seg_lo * N + n] = (Xout)xl;
+    sweep_body<TMAX, Fin, Xout, KIND>(f, X + i0 * N + tile * kWG, lane, N, cnt, cl, xl, cr, xr, T,
+                                      i0, s_f + threadIdx.x, passes);
+
+    // the last workgroup of the launch resets the counters
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = atomicAdd(&sync[1], 1u);
+        if ((int64_t)done == tiles * P - 1) {
+            sync[0] = 0u;
+            sync[1] = 0u;
+            __hip_atomic_store(&sync[2], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ==========================================================================
 // launchers
 static inline dim3 grid2(int64_t N, int64_t y) {
     return dim3((unsigned)((N + kWG - 1) / kWG), (unsigned)y, 1);
@@ -605,6 +823,68 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+int64_t fused_tiles(int64_t N) { return (N + kWG - 1) / kWG; }
+
+template <int TM, typename Fin, typename Xout, int KIND>
+static int64_t fused_occ() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_fused<TM, Fin, Xout, KIND>), kWG,
+                                                     0) != hipSuccess)
+        return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return (int64_t)per_cu * cus;
+}
+
+int64_t fused_resident(int mode, int32_t bucket) {
+    auto pick = [&](auto tm) -> int64_t {
+        constexpr int TM = decltype(tm)::value;
+        switch (mode) {
+            case TDS_F64: return fused_occ<TM, double, double, kSweep64>();
+            case TDS_F32_WIDE: return fused_occ<TM, float, double, kSweep64>();
+            case TDS_F32: return fused_occ<TM, float, float, kSweep32>();
+            default: return fused_occ<TM, float, double, kSweepRefined>();
+        }
+    };
+    if (bucket == 32) return pick(std::integral_constant<int, 32>());
+    if (bucket == 64) return pick(std::integral_constant<int, 64>());
+    return 0;
+}
+
+hipError_t launch_fused(const DevTables& t, const void* F, void* X, int64_t N, int mode,
+                        int passes, double* betaR, double* betaL, double* xsep, unsigned* sync,
+                        int64_t cap, unsigned* status, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    const int64_t tiles = (N + kWG - 1) / kWG;
+    if (tiles > cap) return hipErrorInvalidValue;
+    const int64_t items = tiles * t.P;
+    if (items > 0x7fffffffLL || t.P < 2) return hipErrorInvalidValue;
+    const dim3 g((unsigned)items);
+#define TDS_FUSED(TM, FT, XT, KD)                                                           \
+    hipLaunchKernelGGL((k_fused<TM, FT, XT, KD>), g, dim3(kWG), 0, s, t, (const FT*)F, (XT*)X, \
+                       N, tiles, betaR, betaL, xsep, sync, cap, status, passes)
+#define TDS_FUSED_MODE(TM)                                                                  \
+    switch (mode) {                                                                         \
+        case TDS_F64: TDS_FUSED(TM, double, double, kSweep64); break;                       \
+        case TDS_F32_WIDE: TDS_FUSED(TM, float, double, kSweep64); break;                   \
+        case TDS_F32: TDS_FUSED(TM, float, float, kSweep32); break;                         \
+        default: TDS_FUSED(TM, float, double, kSweepRefined); break;                        \
+    }
+    const int32_t bucket = rows_bucket(t.max_rows);
+    if (bucket == 32) {
+        TDS_FUSED_MODE(32);
+    } else if (bucket == 64) {
+        TDS_FUSED_MODE(64);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef TDS_FUSED_MODE
+#undef TDS_FUSED
     return hipGetLastError();
 }
 
