@@ -40,38 +40,66 @@ def parse():
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
-    p.add_argument("--path", default="auto", choices=["auto", "three", "single"],
-                   help="launch structure: single pass, three kernels, or automatic")
+    p.add_argument("--graph", action="store_true",
+                   help="time replays of a captured HIP graph per step instead of eager launches")
     p.add_argument("--sets", type=int, default=0,
                    help="buffer sets rotated across steps (0: enough to exceed 512 MB)")
     p.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison runs")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="first stream this many MiB through a plain elementwise kernel (read + "
+                        "write of known size) to calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE")
     return p.parse_args()
 
 
-def time_mode(plan, F_sets, X_sets, mode, steps, warmup, torch):
+def time_mode(plan, F_sets, X_sets, mode, steps, warmup, torch, graph):
+    """ms per step over `steps` solves (eager launches, or replays of one
+    captured HIP graph per buffer set), then the per-phase split from a
+    separate eager run with the library's phase events on."""
     n_sets = len(F_sets)
-    for k in range(warmup):
+    for k in range(max(warmup, n_sets)):
         plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
     torch.cuda.synchronize()
-    plan.timing(True)
-    plan.timing_read()                 # clear
+    if graph:
+        graphs = []
+        for k in range(n_sets):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                plan.solve(F_sets[k], X_sets[k], mode=mode)
+            graphs.append(g)
+        for k in range(warmup):
+            graphs[k % n_sets].replay()
+
+        def step(k):
+            graphs[k % n_sets].replay()
+    else:
+        def step(k):
+            plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
     for k in range(steps):
-        plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+        step(k)
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(stop)
+    if graph:
+        del graphs
+    # phase split (events between the launches of each solve)
+    plan.timing(True)
+    plan.timing_read()                 # clear
+    for k in range(min(steps, 20)):
+        plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+    torch.cuda.synchronize()
     ms_beta, ms_iface, ms_sweep, calls = plan.timing_read()
     plan.timing(False)
     return dict(ms_per_step=ms_total / steps, wall_s=wall,
                 ms_beta=ms_beta / calls, ms_iface=ms_iface / calls,
-                ms_sweep=ms_sweep / calls)
+                ms_sweep=ms_sweep / calls, launch="graph" if graph else "eager")
 
 
 def main():
@@ -96,8 +124,14 @@ def main():
         wname = "ADI line solves on a smooth Gaussian random field (b=2.05), FP32 storage"
     a, b, F32 = w["a"], w["b"], w["F"]
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     plan = t.Plan(a, b, P)
-    plan.set_path(args.path)
 
     f_bytes = {"f32_refined": 4, "f32_wide": 4, "f32": 4, "f64": 8}
     x_bytes = {"f32_refined": 8, "f32_wide": 8, "f32": 4, "f64": 8}
@@ -115,8 +149,7 @@ def main():
 
     def run(mode, steps, warmup):
         Fs, Xs = make_sets(mode)
-        r = time_mode(plan, Fs, Xs, mode, steps, warmup, torch)
-        plan.check()
+        r = time_mode(plan, Fs, Xs, mode, steps, warmup, torch, args.graph)
         eta, r2 = plan.residual(Fs[0], Xs[0], mode=mode)
         torch.cuda.synchronize()
         r["eta_max"] = float(eta.max())
@@ -136,10 +169,16 @@ def main():
     sweep_bytes = M * N * (f_bytes[args.mode] + x_bytes[args.mode]) + 2 * (P - 1) * N * 8
     ms_sweep = main_r["ms_sweep"]
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
-    fused = main_r["ms_beta"] + main_r["ms_iface"] < 1e-4
+    kname = "k_sweep_reg"
+    # HBM bytes per launch measured by rocprofv3 counters for this kernel,
+    # mode and workload; null unless taken from the current kernel sources
+    from paper_0901_2859_amd import profdigest
+    tr = profdigest.read_traffic(os.path.join(
+        ROOT, "profiles", f"{kname}_{args.mode}_{args.workload}_{M}x{N}_P{P}_traffic.txt"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_fused" if fused else "k_sweep_reg", "bytes_per_launch": sweep_bytes,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else round(tr[0]),
+                "kernel": kname, "bytes_per_launch": sweep_bytes,
                 "ms_per_launch": round(ms_sweep, 5)}
 
     compare = {}
@@ -181,7 +220,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "M": M, "N": N, "P": P,
                    "mode": args.mode, "layout": "RHS-interleaved [M][N]",
-                   "buffer_sets": main_r["sets"]},
+                   "buffer_sets": main_r["sets"], "launch": main_r["launch"]},
         "hbm_frac_path": round(main_r["path_gbs"] / HBM_PEAK_GBS, 4),
         "path_gbs": round(main_r["path_gbs"], 1),
         "phases_ms": {"beta_interface": round(main_r["ms_beta"] + main_r["ms_iface"], 5),

@@ -141,20 +141,6 @@ int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N,
 int tdsolve_timing_enable(tds_handle h, int32_t on);
 int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
 
-/* Launch structure of tdsolve_series: 0 = automatic (default; currently the
- * three kernels), 1 = three kernels (beta weights, interface step, block
- * sweeps), 2 = single pass (one kernel: every workgroup loads its block of F
- * once, publishes its beta weights, waits for its tile's interface values
- * and sweeps; used only when the plan's blocks have at most 64 rows and P is
- * at most half of the workgroups the device holds at once -- otherwise the
- * three kernels run).  Both give the same results up to rounding order. */
-int tdsolve_set_path(tds_handle h, int32_t path);
-
-/* Waits for the device and reports whether a single-pass launch of the
- * handle hit its bounded wait (TDS_EHIP; the flag is then cleared, and the
- * results of that launch are not valid).  TDS_OK otherwise. */
-int tdsolve_check(tds_handle h);
-
 /* Number of refinement passes for TDS_F32_REFINED (0..8; default 2). */
 int tdsolve_set_refinement(tds_handle h, int32_t passes);
 

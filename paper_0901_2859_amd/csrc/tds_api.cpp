@@ -25,12 +25,6 @@ struct tds_plan {
     bool timing = false;         // record per-phase events
     std::vector<hipEvent_t> events;  // 4 per timed call
     size_t events_used = 0;
-    // single-pass kernel: control words (zeroed once), timeout flag, choice
-    unsigned* sync = nullptr;
-    int64_t sync_cap = 0;                // tile capacity of the control area
-    unsigned* status = nullptr;
-    int32_t path = 0;                    // 0 auto, 1 three kernels, 2 single pass
-    int64_t resident[4] = {-1, -1, -1, -1};
     // batch handles: K matrices sharing one table allocation
     bool is_batch = false;
     int32_t bucket = 0;                  // common register-sweep row bucket
@@ -62,8 +56,6 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     const size_t o_a64 = take(sizeof(double) * MR), o_b64 = take(sizeof(double) * MR);
     const size_t o_cp64 = take(sizeof(double) * MR), o_rd64 = take(sizeof(double) * MR);
     const size_t o_wpad = take(sizeof(double) * 2 * (size_t)P * (size_t)(WP > 0 ? WP : 1));
-    const size_t o_wint = take(sizeof(double) * 2 * (size_t)P * (size_t)(WP > 0 ? WP : 1));
-    const size_t o_wsep = take(sizeof(double) * 2 * (size_t)P);
     const size_t o_in64 = take(sizeof(double) * MR), o_u = take(sizeof(double) * MR);
     const size_t o_v = take(sizeof(double) * MR);
     const size_t o_a32 = take(sizeof(float) * MR), o_cp32 = take(sizeof(float) * MR);
@@ -101,22 +93,6 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
                 wp[2 * r + 1] = o.wL[i];
             }
         put(o_wpad, wp.data(), sizeof(double) * wp.size());
-        // split form: the interface row s_j apart, interior rows from 0
-        std::vector<double> wi(2 * (size_t)P * WP, 0.0), ws(2 * (size_t)P, 0.0);
-        for (int32_t j = 0; j < P; ++j) {
-            const int64_t i0 = (j == 0) ? o.starts[0] : o.starts[j] + 1;
-            if (j > 0) {
-                ws[2 * j] = o.wR[o.starts[j]];
-                ws[2 * j + 1] = o.wL[o.starts[j]];
-            }
-            for (int64_t i = i0; i < o.starts[j + 1]; ++i) {
-                const size_t r = (size_t)j * WP + (size_t)(i - i0);
-                wi[2 * r] = o.wR[i];
-                wi[2 * r + 1] = o.wL[i];
-            }
-        }
-        put(o_wint, wi.data(), sizeof(double) * wi.size());
-        put(o_wsep, ws.data(), sizeof(double) * ws.size());
     }
     std::vector<double> in(o.a64);
     for (int32_t j = 0; j < P; ++j) in[o.starts[j + 1] - 1] = 0.0;   // block ends
@@ -143,8 +119,6 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     d.rd64 = (double*)o_rd64;
     d.wpad = (const double2*)o_wpad;
     d.wpad_rows = WP;
-    d.wint = (const double2*)o_wint;
-    d.wsep = (const double2*)o_wsep;
     d.in64 = (double*)o_in64;
     d.u = (double*)o_u;
     d.v = (double*)o_v;
@@ -164,7 +138,6 @@ void rebase(DevTables& d, void* mem) {
     unsigned char* b = (unsigned char*)mem;
     shift(d.starts, b); shift(d.wR, b); shift(d.wL, b); shift(d.rho, b); shift(d.lam, b);
     shift(d.a64, b); shift(d.b64, b); shift(d.cp64, b); shift(d.rd64, b); shift(d.wpad, b);
-    shift(d.wint, b); shift(d.wsep, b);
     shift(d.in64, b); shift(d.u, b); shift(d.v, b); shift(d.a32, b); shift(d.cp32, b);
     shift(d.rd32, b); shift(d.in32, b);
 }
@@ -243,41 +216,6 @@ hipEvent_t* timing_slot(tds_plan* h) {
     return ev;
 }
 
-int ensure_sync(tds_plan* h, int64_t N) {
-    const int64_t tiles = fused_tiles(N);
-    if (!h->status) {
-        if (hipMalloc(&h->status, 256) != hipSuccess) return TDS_ENOMEM;
-        if (hipMemset(h->status, 0, 256) != hipSuccess) return TDS_EHIP;
-    }
-    if (tiles <= h->sync_cap) return TDS_OK;
-    if (h->sync) {
-        if (hipDeviceSynchronize() != hipSuccess) return TDS_EHIP;
-        (void)hipFree(h->sync);
-        h->sync = nullptr;
-        h->sync_cap = 0;
-    }
-    const int64_t cap = std::max<int64_t>(tiles, 64);
-    const size_t bytes = sizeof(unsigned) * (size_t)(4 + 2 * cap);
-    if (hipMalloc(&h->sync, bytes) != hipSuccess) return TDS_ENOMEM;
-    if (hipMemset(h->sync, 0, bytes) != hipSuccess) return TDS_EHIP;
-    h->sync_cap = cap;
-    return TDS_OK;
-}
-
-// single pass when the plan allows it: 2 <= P, blocks of at most 64 rows
-// (refined: 64, others: 64) and P at most half of the resident workgroups
-bool use_fused(tds_plan* h, int32_t mode) {
-    // automatic choice: three kernels (measured faster on the 4096 x 4096
-    // Poisson series: the tile-wide wait of the single pass leaves its
-    // workgroups idle while the last one of the tile runs the recurrences)
-    if (h->path != 2) return false;
-    const DevTables& t = h->dev;
-    const int32_t bucket = rows_bucket(t.max_rows);
-    if (t.P < 2 || (bucket != 32 && bucket != 64)) return false;
-    if (h->resident[mode] < 0) h->resident[mode] = fused_resident(mode, bucket);
-    return (int64_t)t.P * 2 <= h->resident[mode];
-}
-
 int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hipStream_t s,
                 int sweep_mode) {
     const DevTables& t = h->dev;
@@ -290,17 +228,6 @@ int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hi
     double* xsep = (double*)(general_of(h) + 2 * nb);
     hipEvent_t* ev = timing_slot(h);
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TDS_EHIP;
-    if (use_fused(h, sweep_mode)) {
-        rc = ensure_sync(h, N);
-        if (rc) return rc;
-        if (ev && (hipEventRecord(ev[1], s) != hipSuccess || hipEventRecord(ev[2], s) != hipSuccess))
-            return TDS_EHIP;
-        if (launch_fused(t, F, X, N, sweep_mode, h->passes, betaR, betaL, xsep, h->sync,
-                         h->sync_cap, h->status, s) != hipSuccess)
-            return TDS_EHIP;
-        if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TDS_EHIP;
-        return TDS_OK;
-    }
     if (t.P >= 2) {
         if (launch_beta(t, F, mode != TDS_F64, N, betaR, betaL, s) != hipSuccess) return TDS_EHIP;
         if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TDS_EHIP;
@@ -318,6 +245,21 @@ __global__ void k_cast_f32(const double* __restrict__ src, float* __restrict__ d
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = i; k < n; k += stride) dst[k] = (float)src[k];
+}
+
+// zero fill by a kernel (not a memset node, so that captured graphs replay it
+// reliably)
+__global__ void k_zero_f64(double* __restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride) dst[k] = 0.0;
+}
+
+hipError_t zero_f64(double* p, int64_t n, hipStream_t s) {
+    if (!p || n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_f64, dim3(blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -374,8 +316,8 @@ int tdsolve_backward(tds_handle h, const void* X, const void* gX, void* gF, doub
     if (rc) return rc;
     if (N == 0) {
         hipStream_t s = (hipStream_t)stream;
-        if (ga && h->dev.M > 1 && hipMemsetAsync(ga, 0, sizeof(double) * (h->dev.M - 1), s) != hipSuccess) return TDS_EHIP;
-        if (gb && hipMemsetAsync(gb, 0, sizeof(double) * h->dev.M, s) != hipSuccess) return TDS_EHIP;
+        if (zero_f64(ga, h->dev.M - 1, s) != hipSuccess) return TDS_EHIP;
+        if (zero_f64(gb, h->dev.M, s) != hipSuccess) return TDS_EHIP;
         return TDS_OK;
     }
     if (!X || !gX || !gF) return TDS_EINVAL;
@@ -452,26 +394,6 @@ int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls) {
     return TDS_OK;
 }
 
-int tdsolve_set_path(tds_handle h, int32_t path) {
-    if (!h || h->is_batch || path < 0 || path > 2) return TDS_EINVAL;
-    h->path = path;
-    return TDS_OK;
-}
-
-int tdsolve_check(tds_handle h) {
-    if (!h) return TDS_EINVAL;
-    if (!h->status) return TDS_OK;
-    if (hipDeviceSynchronize() != hipSuccess) return TDS_EHIP;
-    unsigned st = 0;
-    if (hipMemcpy(&st, h->status, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
-        return TDS_EHIP;
-    if (st) {
-        if (hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) return TDS_EHIP;
-        return TDS_EHIP;
-    }
-    return TDS_OK;
-}
-
 int tdsolve_set_refinement(tds_handle h, int32_t passes) {
     if (!h || passes < 0 || passes > 8) return TDS_EINVAL;
     h->passes = passes;
@@ -507,13 +429,11 @@ int32_t tdsolve_default_blocks(int64_t M) { return default_blocks(M); }
 
 int tdsolve_destroy(tds_handle h) {
     if (!h) return TDS_EINVAL;
-    if (h->work || h->dev_mem || h->sync) (void)hipDeviceSynchronize();
+    if (h->work || h->dev_mem) (void)hipDeviceSynchronize();
     if (h->work) (void)hipFree(h->work);
     if (h->dev_mem) (void)hipFree(h->dev_mem);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->d_desc) (void)hipFree(h->d_desc);
-    if (h->sync) (void)hipFree(h->sync);
-    if (h->status) (void)hipFree(h->status);
     delete h;
     return TDS_OK;
 }
@@ -588,7 +508,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         bytes += 2 * nb + align256(sizeof(double) * (size_t)(t.P > 1 ? t.P - 1 : 1) * (size_t)n);
         if (n > 0) {
             items += (int64_t)t.P * ((n + kWG - 1) / kWG);
-            if (t.P > 1) scans += (n + 63) / 64;
+            if (t.P > 1) scans += (n + kScanRhs - 1) / kScanRhs;
         }
     }
     if (items == 0) return TDS_OK;

@@ -12,6 +12,7 @@ namespace tds {
 // Workgroup size of every per-block kernel: 4 wavefronts of 64 lanes, each
 // lane one right-hand side.
 constexpr int kWG = 256;
+constexpr int kScanRhs = 16;      // right-hand sides per interface-scan workgroup
 
 // Largest block (rows of one segment) handled by the register-resident
 // sweep; larger blocks take the streaming sweep, which keeps the forward
@@ -45,11 +46,6 @@ struct DevTables {
     double* v = nullptr;
     const double2* wpad = nullptr;         // beta weights (wR, wL) per block,
     int32_t wpad_rows = 0;                 //   padded to wpad_rows with zeros
-    // the same weights split for the single-pass kernel: wsep[j] = weights
-    // of block j's interface row s_j (zero for j = 0), wint[j][r] = weights
-    // of its r-th interior row, zero-padded to wpad_rows rows
-    const double2* wsep = nullptr;
-    const double2* wint = nullptr;
     float* a32 = nullptr;
     float* cp32 = nullptr;
     float* rd32 = nullptr;
@@ -110,18 +106,6 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items,
                         int64_t scans, int32_t bucket, int mode, int passes,
                         hipStream_t s);
 
-// Single-pass solve (beta, interface step and block sweeps in one launch).
-// `sync` points to a zero-initialised control area of 4 + 2 * cap words
-// (cap >= fused_tiles(N)) that every launch leaves ready for the next one;
-// `status` word 0 is set non-zero if a wait ran into its bound.  Requires
-// 2 <= P and blocks of at most 64 rows.
-int64_t fused_tiles(int64_t N);
-hipError_t launch_fused(const DevTables& t, const void* F, void* X, int64_t N,
-                        int mode, int passes, double* betaR, double* betaL,
-                        double* xsep, unsigned* sync, int64_t cap,
-                        unsigned* status, hipStream_t s);
-// workgroups of the single-pass kernel the current device keeps resident
-int64_t fused_resident(int mode, int32_t bucket);
 hipError_t launch_residual(const DevTables& t, const void* F, const void* X,
                            int64_t N, int mode, double normA, double* part,
                            double* out, hipStream_t s);

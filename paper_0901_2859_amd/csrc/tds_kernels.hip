@@ -53,64 +53,87 @@ __device__ __forceinline__ const T& at_off(const T* base, uint32_t byte_off) {
 }
 
 // ==========================================================================
-// beta weights (eq. beta_symn).  Item (tile, j): block j of rows x 256
-// consecutive right-hand sides, one per lane.  All rows of the block are
-// loaded before any arithmetic (one round trip to memory per item); rows
-// past the block re-read its last row and get weight zero from the
-// zero-padded per-block weight table.
+// beta weights (eq. beta_symn).  Item (tile, j): block j of rows x 64
+// consecutive right-hand sides (one per lane); the four wavefronts of the
+// workgroup take one quarter of the block's rows each, so every wavefront
+// keeps only a quarter of the rows in flight and the grid holds four times
+// as many wavefronts as one wavefront per 64 right-hand sides would.  All
+// rows of a quarter are loaded before any arithmetic (one round trip to
+// memory); rows past the block re-read its last row and get weight zero from
+// the zero-padded per-block weight table.  The four partial sums meet in LDS
+// and are added in a fixed order (results do not depend on timing).
+constexpr int kBetaRhs = 64;
+constexpr int kBetaWaves = kWG / kBetaRhs;
+
 template <int TMAX, typename Fin>
 __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restrict__ F,
                                           int64_t N, int32_t j, int64_t tile,
                                           double* __restrict__ betaR,
-                                          double* __restrict__ betaL) {
+                                          double* __restrict__ betaL,
+                                          double2* __restrict__ red) {
+    const int64_t n0 = tile * kBetaRhs;
+    if (n0 >= N) return;                                  // uniform per workgroup
     const int64_t lo = cst(T.starts)[j];
     const int t = (int)(cst(T.starts)[j + 1] - lo);
-    const int lane = threadIdx.x;
-    const int64_t n = tile * kWG + lane;
-    if (n >= N) return;
-    // wave-uniform row bases plus one 32-bit lane offset: the loads use the
-    // scalar-base addressing form instead of a 64-bit address per row
-    const Fin* fb = F + lo * N + tile * kWG;
-    const Fin* f = fb + lane;
+    const int lane = threadIdx.x % kBetaRhs;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kBetaRhs);
+    const bool live = n0 + lane < N;
+    // wave-uniform row bases plus one 32-bit byte offset per lane (lanes past
+    // N read column N-1 and store nothing)
+    const uint32_t off = (uint32_t)(live ? lane : N - 1 - n0) * sizeof(Fin);
+    const Fin* fb = F + lo * N + n0;
     double bR = 0.0, bL = 0.0;
     if constexpr (TMAX > 0) {
-        const cptr<double2> w = cst(T.wpad + (int64_t)j * TMAX);
-        Fin v[TMAX];
+        constexpr int TQ = TMAX / kBetaWaves;
+        const int r0 = wv * TQ;
+        const cptr<double2> w = cst(T.wpad + (int64_t)j * TMAX + r0);
+        Fin v[TQ];
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r)
-            v[r] = at_off(fb + (int64_t)(r < t ? r : t - 1) * N, (uint32_t)lane * sizeof(Fin));
+        for (int r = 0; r < TQ; ++r) {
+            const int row = r0 + r < t ? r0 + r : t - 1;
+            v[r] = at_off(fb + (int64_t)row * N, off);
+        }
 #pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            // convert each value next to its use: converting all of them as
-            // they arrive would double the registers the loads occupy
-            if ((r & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        for (int r = 0; r < TQ; ++r) {
             const double cR = w[r].x, cL = w[r].y;
             bR = fma(cR, (double)v[r], bR);
             bL = fma(cL, (double)v[r], bL);
         }
     } else {
+        const int q = (t + kBetaWaves - 1) / kBetaWaves;
+        const int r0 = wv * q, r1 = r0 + q < t ? r0 + q : t;
         const cptr<double> gR = cst(T.wR + lo);
         const cptr<double> gL = cst(T.wL + lo);
         constexpr int U = 16;
-        int r = 0;
-        for (; r + U <= t; r += U) {
+        int r = r0;
+        for (; r + U <= r1; r += U) {
             Fin v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = f[(int64_t)(r + u) * N];
+            for (int u = 0; u < U; ++u) v[u] = at_off(fb + (int64_t)(r + u) * N, off);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 bR = fma(gR[r + u], (double)v[u], bR);
                 bL = fma(gL[r + u], (double)v[u], bL);
             }
         }
-        for (; r < t; ++r) {
-            const double v = (double)f[(int64_t)r * N];
+        for (; r < r1; ++r) {
+            const double v = (double)at_off(fb + (int64_t)r * N, off);
             bR = fma(gR[r], v, bR);
             bL = fma(gL[r], v, bL);
         }
     }
-    if (j < T.P - 1) betaR[(int64_t)j * N + n] = bR;
-    if (j > 0) betaL[(int64_t)j * N + n] = bL;
+    if (wv > 0) red[(wv - 1) * kBetaRhs + lane] = make_double2(bR, bL);
+    __syncthreads();
+    if (wv == 0 && live) {
+#pragma unroll
+        for (int k = 0; k < kBetaWaves - 1; ++k) {
+            const double2 p = red[k * kBetaRhs + lane];
+            bR += p.x;
+            bL += p.y;
+        }
+        if (j < T.P - 1) betaR[(int64_t)j * N + n0 + lane] = bR;
+        if (j > 0) betaL[(int64_t)j * N + n0 + lane] = bL;
+    }
 }
 
 // ==========================================================================
@@ -120,20 +143,22 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
 //   backward  z_j = lam_j z_{j+1} + beta^L_j,  j = P-1..1 (z_P = 0),
 //             so that S^L_j = z_j;
 //   x(s_k) = S^R_k + S^L_k, k = 1..P-1  (xsep row k-1),
-// as a two-level scan: workgroup = 64 right-hand sides x up to 16 groups of
-// `per` consecutive blocks.  Each thread loads its group's beta values once,
-// scans them with zero input, the group carries (product of the factors,
-// partial value) are combined through LDS, then each thread finishes its
-// group with the true input.  S^R is written to xsep first; after a
-// workgroup barrier the thread owning the same interface row in the
-// backward direction adds S^L.
-constexpr int kScanRhs = 64;
+// as a two-level scan: workgroup = 16 right-hand sides x up to 16 groups of
+// `per` consecutive blocks (a wavefront covers 4 groups; each group's row
+// access is one 128-byte line).  Each thread loads its group's beta values
+// once, scans them with zero input, the group carries (product of the
+// factors, partial value) are combined through LDS, then each thread
+// finishes its group with the true input.  When a thread keeps its beta
+// values in registers (per <= 8), S^R goes to LDS and the thread owning the
+// same interface row in the backward direction writes S^R + S^L to xsep
+// once; otherwise S^R is written to xsep and S^L added after a barrier.
 constexpr int kScanMaxGroups = 16;
 constexpr int kScanMaxPer = 8;     // beta values a thread keeps in registers
 
 struct ScanLDS {
     double carry[2][kScanMaxGroups][kScanRhs];
     double prod[2][kScanMaxGroups];
+    double sr[kScanMaxGroups * kScanMaxPer][kScanRhs];
 };
 
 __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_t per,
@@ -195,7 +220,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
         yin = fma(S.prod[0][q], yin, S.carry[0][q][lane]);
         zin = fma(S.prod[1][q], zin, S.carry[1][q][lane]);
     }
-    // finish the forward group: y_j = S^R_{j+1} into xsep
+    // finish the forward group: y_j = S^R_{j+1} into LDS or xsep
     if (live) {
         double y = yin;
         if (keep) {
@@ -204,7 +229,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
                 const int32_t j = f0 + u;
                 if (j < f1) {
                     y = fma((j > 0) ? rho[j] : 0.0, y, bRv[u]);
-                    xsep[(int64_t)j * N + n] = y;
+                    S.sr[j][lane] = y;
                 }
             }
         } else {
@@ -214,7 +239,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             }
         }
     }
-    __syncthreads();     // S^R of every group is in xsep (same workgroup)
+    __syncthreads();     // S^R of every group is in LDS or xsep (same workgroup)
     if (!live) return;
     double z = zin;
     if (keep) {
@@ -223,13 +248,13 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             const int32_t j = b1 - u;
             if (j > b0) {
                 z = fma((j < P - 1) ? lam[j] : 0.0, z, bLv[u]);
-                xsep[(int64_t)(j - 1) * N + n] += z;       // x(s_j) = S^R_j + S^L_j
+                xsep[(int64_t)(j - 1) * N + n] = S.sr[j - 1][lane] + z;   // S^R_j + S^L_j
             }
         }
     } else {
         for (int32_t j = b1; j > b0; --j) {
             z = fma((j < P - 1) ? lam[j] : 0.0, z, betaL[(int64_t)j * N + n]);
-            xsep[(int64_t)(j - 1) * N + n] += z;
+            xsep[(int64_t)(j - 1) * N + n] += z;       // x(s_j) = S^R_j + S^L_j
         }
     }
 }
@@ -457,7 +482,8 @@ template <int TMAX, typename Fin>
 __global__ __launch_bounds__(kWG) void k_beta(DevTables T, const Fin* __restrict__ F, int64_t N,
                                               double* __restrict__ betaR,
                                               double* __restrict__ betaL) {
-    beta_item<TMAX, Fin>(T, F, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, betaR, betaL);
+    __shared__ double2 red[(kBetaWaves - 1) * kBetaRhs];
+    beta_item<TMAX, Fin>(T, F, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, betaR, betaL, red);
 }
 
 __global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface(
@@ -506,16 +532,20 @@ __device__ __forceinline__ int32_t find_desc(const BatchDesc* __restrict__ D, in
     return lo;
 }
 
+// the beta launch has kBetaWaves workgroups per item (one per 64-RHS
+// quarter of the item's 256 right-hand sides)
 template <int TMAX, typename Fin>
 __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict__ D, int32_t K) {
-    const int64_t item = blockIdx.x;
+    __shared__ double2 red[(kBetaWaves - 1) * kBetaRhs];
+    const int64_t item = blockIdx.x / kBetaWaves;
+    const int32_t sub = blockIdx.x % kBetaWaves;
     const int32_t k = find_desc(D, K, item, false);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
     if (d.T.P < 2 || local >= (int64_t)d.T.P * tiles) return;
-    beta_item<TMAX, Fin>(d.T, (const Fin*)d.F, d.N, (int32_t)(local / tiles), local % tiles,
-                         d.betaR, d.betaL);
+    beta_item<TMAX, Fin>(d.T, (const Fin*)d.F, d.N, (int32_t)(local / tiles),
+                         (local % tiles) * kBetaWaves + sub, d.betaR, d.betaL, red);
 }
 
 __global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface_batch(
@@ -545,199 +575,6 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 }
 
 // ==========================================================================
-// Single-pass solve: beta, interface step and block sweep in one launch.
-//
-// Every workgroup owns one item (RHS tile, block j), taken from a ticket
-// counter in tile-major order, so the P blocks of a tile are dispatched
-// together.  It loads the block's rows of F once (kept in registers), forms
-// beta^R_j, beta^L_j, publishes them and counts itself in at its tile.  The
-// last of the tile's P workgroups to arrive runs the tile's interface step
-// (the two recurrences, serially per right-hand side) and raises the tile's
-// ready word to this launch's generation; the others wait for it, then all
-// sweep their block from the rows still in registers and write X.  F is read
-// from memory once.
-//
-// Progress: a workgroup only waits for tickets of its own tile, tickets are
-// taken in order, and every taken ticket publishes before waiting; so as long
-// as P workgroups fit on the device at once the tile's last ticket is always
-// taken and the wait ends.  The host only uses this kernel when P is at most
-// half of the resident capacity; the wait is also bounded (status flag).
-//
-// Control words (zeroed once; every launch leaves them ready for the next):
-//   sync[0] ticket counter, sync[1] finished workgroups, sync[2] generation of
-//   the last completed launch, sync[4 + tile] arrivals per tile,
-//   sync[4 + cap + tile] ready generation per tile, where cap is the tile
-//   capacity of the control area (fixed for its lifetime, so the positions
-//   do not move when N changes between launches).
-// Lanes past N compute on column N-1 and store the same values as its own
-// lane (plain stores of identical values), so the loads and the sweep need
-// no masking; only the in-place interface scan is restricted to live lanes.
-constexpr unsigned kSpinLimit = 1u << 20;
-
-// Cross-workgroup data of the single pass moves with device-coherent
-// (relaxed, agent-scope) loads and stores, which bypass the per-XCD L2
-// instead of needing whole-cache write-back / invalidate fences; ordering
-// comes from waiting for the stores' completion before the counter update
-// and from the control dependence on the counter / ready word.
-__device__ __forceinline__ void st_dev(double* p, double v) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_dev(const double* p) {
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-// wait until this wavefront's stores are complete
-__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-// CH interface values per lane are loaded per round trip
-template <int CH>
-__device__ __forceinline__ void tile_scan(const DevTables& T, int64_t N, int64_t n,
-                                          const double* betaR, const double* betaL,
-                                          double* xsep) {
-    const int32_t P = T.P;
-    const cptr<double> rho = cst(T.rho), lam = cst(T.lam);
-    double SR = 0.0;
-    for (int32_t k0 = 0; k0 <= P - 2; k0 += CH) {
-        double bv[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u)
-            if (k0 + u <= P - 2) bv[u] = ld_dev(betaR + (int64_t)(k0 + u) * N + n);
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int32_t k = k0 + u;
-            if (k <= P - 2) {
-                SR = (k == 0) ? bv[u] : fma(rho[k], SR, bv[u]);
-                st_dev(xsep + (int64_t)k * N + n, SR);              // S^R_{k+1}
-            }
-        }
-    }
-    double SL = 0.0;
-    for (int32_t k1 = P - 1; k1 >= 1; k1 -= CH) {
-        double bv[CH], sr[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int32_t k = k1 - u;
-            if (k >= 1) {
-                bv[u] = ld_dev(betaL + (int64_t)k * N + n);
-                sr[u] = ld_dev(xsep + (int64_t)(k - 1) * N + n);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int32_t k = k1 - u;
-            if (k >= 1) {
-                SL = (k == P - 1) ? bv[u] : fma(lam[k], SL, bv[u]);
-                st_dev(xsep + (int64_t)(k - 1) * N + n, sr[u] + SL);   // x(s_k)
-            }
-        }
-    }
-}
-
-template <int TMAX, typename Fin, typename Xout, int KIND>
-__global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_fused(
-    DevTables T, const Fin* __restrict__ F, Xout* __restrict__ X, int64_t N, int64_t tiles,
-    double* betaR, double* betaL, double* xsep, unsigned* sync, int64_t cap, unsigned* status,
-    int passes) {
-    __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
-    __shared__ unsigned s_item, s_gen, s_last;
-    const int32_t P = T.P;
-    if (threadIdx.x == 0) {
-        s_item = atomicAdd(&sync[0], 1u);
-        s_gen = __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const int64_t item = s_item;
-    const unsigned gen = s_gen + 1u;
-    const int64_t tile = item / P;
-    const int32_t j = (int32_t)(item - tile * P);
-    unsigned* arrive = sync + 4;
-    unsigned* ready = sync + 4 + cap;
-
-    const int64_t seg_lo = cst(T.starts)[j], seg_hi = cst(T.starts)[j + 1];
-    const int64_t i0 = (j == 0) ? seg_lo : seg_lo + 1;
-    const int cnt = (int)(seg_hi - i0);
-    const int64_t n0 = tile * kWG + threadIdx.x;
-    const int64_t n = n0 < N ? n0 : N - 1;
-    const int lane = (int)(n - tile * kWG);
-
-    // the block's rows of F, once
-    Fin f[TMAX];
-    sweep_load<TMAX, Fin>(F + i0 * N + tile * kWG, lane, N, cnt, f);
-    const double fs = (j > 0) ? (double)F[seg_lo * N + n] : 0.0;
-
-    // beta weights of the segment (eq. beta_symn)
-    {
-        const cptr<double2> w = cst(T.wint + (int64_t)j * TMAX);
-        double bR = cst(T.wsep)[j].x * fs, bL = cst(T.wsep)[j].y * fs;
-#pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            const double wr = w[r].x, wl = w[r].y;
-            bR = fma(wr, (double)f[r], bR);
-            bL = fma(wl, (double)f[r], bL);
-        }
-        if (j < P - 1) st_dev(betaR + (int64_t)j * N + n, bR);
-        if (j > 0) st_dev(betaL + (int64_t)j * N + n, bL);
-    }
-    stores_done();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(&arrive[tile], 1u);
-        s_last = (prev == (unsigned)(P - 1)) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (s_last) {
-        // interface step of the tile (Theorem 2); only live lanes: the
-        // backward pass updates xsep in place, which a duplicate lane in
-        // another wavefront would apply twice
-        // (the refined sweep needs more registers anyway, so its scan can
-        // keep twice as many values in flight)
-        if (n0 < N) tile_scan<KIND == kSweepRefined ? 32 : 16>(T, N, n, betaR, betaL, xsep);
-        stores_done();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            arrive[tile] = 0u;
-            __hip_atomic_store(&ready[tile], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else {
-        if (threadIdx.x == 0) {
-            // poll with relaxed device-scope loads (no cache invalidation)
-            unsigned spins = 0;
-            while (__hip_atomic_load(&ready[tile], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-                   gen) {
-                if (++spins > kSpinLimit) {
-                    atomicOr(status, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-        }
-        __syncthreads();
-    }
-
-    // block sweep with the interface values known (Lemma 1)
-    const double xl = (j > 0) ? ld_dev(xsep + (int64_t)(j - 1) * N + n) : 0.0;
-    const double xr = (j < P - 1) ? ld_dev(xsep + (int64_t)j * N + n) : 0.0;
-    const double cl = (j > 0) ? cst(T.a64)[i0 - 1] : 0.0;
-    const double cr = (j < P - 1) ? cst(T.a64)[seg_hi - 1] : 0.0;
-    if (j > 0) X[seg_lo * N + n] = (Xout)xl;
-    sweep_body<TMAX, Fin, Xout, KIND>(f, X + i0 * N + tile * kWG, lane, N, cnt, cl, xl, cr, xr, T,
-                                      i0, s_f + threadIdx.x, passes);
-
-    // the last workgroup of the launch resets the counters
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned done = atomicAdd(&sync[1], 1u);
-        if ((int64_t)done == tiles * P - 1) {
-            sync[0] = 0u;
-            sync[1] = 0u;
-            __hip_atomic_store(&sync[2], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// ==========================================================================
 // launchers
 static inline dim3 grid2(int64_t N, int64_t y) {
     return dim3((unsigned)((N + kWG - 1) / kWG), (unsigned)y, 1);
@@ -750,7 +587,7 @@ int32_t rows_bucket(int32_t max_rows) {
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
                        double* betaL, hipStream_t s) {
     if (t.P < 2 || N == 0) return hipSuccess;
-    const dim3 g = grid2(N, t.P);
+    const dim3 g((unsigned)((N + kBetaRhs - 1) / kBetaRhs), (unsigned)t.P, 1);
 #define TDS_BETA(TM, FT) \
     hipLaunchKernelGGL((k_beta<TM, FT>), g, dim3(kWG), 0, s, t, (const FT*)F, N, betaR, betaL)
     switch (t.wpad_rows) {
@@ -826,68 +663,6 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
     return hipGetLastError();
 }
 
-int64_t fused_tiles(int64_t N) { return (N + kWG - 1) / kWG; }
-
-template <int TM, typename Fin, typename Xout, int KIND>
-static int64_t fused_occ() {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_fused<TM, Fin, Xout, KIND>), kWG,
-                                                     0) != hipSuccess)
-        return 0;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    return (int64_t)per_cu * cus;
-}
-
-int64_t fused_resident(int mode, int32_t bucket) {
-    auto pick = [&](auto tm) -> int64_t {
-        constexpr int TM = decltype(tm)::value;
-        switch (mode) {
-            case TDS_F64: return fused_occ<TM, double, double, kSweep64>();
-            case TDS_F32_WIDE: return fused_occ<TM, float, double, kSweep64>();
-            case TDS_F32: return fused_occ<TM, float, float, kSweep32>();
-            default: return fused_occ<TM, float, double, kSweepRefined>();
-        }
-    };
-    if (bucket == 32) return pick(std::integral_constant<int, 32>());
-    if (bucket == 64) return pick(std::integral_constant<int, 64>());
-    return 0;
-}
-
-hipError_t launch_fused(const DevTables& t, const void* F, void* X, int64_t N, int mode,
-                        int passes, double* betaR, double* betaL, double* xsep, unsigned* sync,
-                        int64_t cap, unsigned* status, hipStream_t s) {
-    if (N == 0) return hipSuccess;
-    const int64_t tiles = (N + kWG - 1) / kWG;
-    if (tiles > cap) return hipErrorInvalidValue;
-    const int64_t items = tiles * t.P;
-    if (items > 0x7fffffffLL || t.P < 2) return hipErrorInvalidValue;
-    const dim3 g((unsigned)items);
-#define TDS_FUSED(TM, FT, XT, KD)                                                           \
-    hipLaunchKernelGGL((k_fused<TM, FT, XT, KD>), g, dim3(kWG), 0, s, t, (const FT*)F, (XT*)X, \
-                       N, tiles, betaR, betaL, xsep, sync, cap, status, passes)
-#define TDS_FUSED_MODE(TM)                                                                  \
-    switch (mode) {                                                                         \
-        case TDS_F64: TDS_FUSED(TM, double, double, kSweep64); break;                       \
-        case TDS_F32_WIDE: TDS_FUSED(TM, float, double, kSweep64); break;                   \
-        case TDS_F32: TDS_FUSED(TM, float, float, kSweep32); break;                         \
-        default: TDS_FUSED(TM, float, double, kSweepRefined); break;                        \
-    }
-    const int32_t bucket = rows_bucket(t.max_rows);
-    if (bucket == 32) {
-        TDS_FUSED_MODE(32);
-    } else if (bucket == 64) {
-        TDS_FUSED_MODE(64);
-    } else {
-        return hipErrorInvalidValue;
-    }
-#undef TDS_FUSED_MODE
-#undef TDS_FUSED
-    return hipGetLastError();
-}
-
 template <int TM>
 static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, int passes,
                         hipStream_t s) {
@@ -916,7 +691,8 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
                         int32_t bucket, int mode, int passes, hipStream_t s) {
     if (items == 0) return hipSuccess;
     if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
-    const dim3 g((unsigned)items);
+    if (items > INT32_MAX / kBetaWaves) return hipErrorInvalidValue;
+    const dim3 g((unsigned)(items * kBetaWaves));
     const bool f64in = (mode == TDS_F64);
     if (bucket == 32) {
         if (f64in)

@@ -28,7 +28,7 @@ SYMBOLS = [
     "tdsolve_residual", "tdsolve_set_refinement", "tdsolve_info", "tdsolve_prepare_host",
     "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
-    "tdsolve_timing_read", "tdsolve_set_path", "tdsolve_check",
+    "tdsolve_timing_read",
 ]
 
 _lib = None
@@ -73,8 +73,6 @@ def lib():
     L.tdsolve_batch_prepare.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(vp)]
     L.tdsolve_batch_series.argtypes = [vp, vp, vp, vp, i32, vp]
     L.tdsolve_timing_enable.argtypes = [vp, i32]
-    L.tdsolve_set_path.argtypes = [vp, i32]
-    L.tdsolve_check.argtypes = [vp]
     L.tdsolve_timing_read.argtypes = [vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("tdsolve_default_blocks", "tdsolve_strerror"):
@@ -160,15 +158,6 @@ class Plan:
         calls = np.zeros(1, dtype=np.int64)
         _check(lib().tdsolve_timing_read(self._h, _ptr(ms), _ptr(calls)), "tdsolve_timing_read")
         return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
-
-    def set_path(self, path):
-        """'auto' (default), 'three' (three kernels) or 'single' (one pass)."""
-        code = {"auto": 0, "three": 1, "single": 2}[path] if isinstance(path, str) else int(path)
-        _check(lib().tdsolve_set_path(self._h, code), "tdsolve_set_path")
-
-    def check(self):
-        """Raise if a single-pass launch ran into its bounded wait."""
-        _check(lib().tdsolve_check(self._h), "tdsolve_check")
 
     def set_refinement(self, passes: int):
         _check(lib().tdsolve_set_refinement(self._h, int(passes)), "tdsolve_set_refinement")
