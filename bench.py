@@ -1,13 +1,17 @@
 """Benchmark: unknowns solved per second for a series of symmetric
 tridiagonal systems on one MI355X, FP32-refined path vs plain FP64 path.
 
-Workload: 1-D Poisson series, M = 4096 rows, N = 4096 right-hand sides
-(each a sum of 8 random sine modes plus U[-1e-3, 1e-3] noise, stored as
-FP32), P = 64 blocks of 64 rows, RHS-interleaved layout.  One step = one
+Default workload: 1-D Poisson series, M = 4096 rows, N = 4096 right-hand
+sides (each a sum of 8 random sine modes plus U[-1e-3, 1e-3] noise, stored
+as FP32), P = 64 blocks of 64 rows, RHS-interleaved layout.  One step = one
 full solve of the series (beta weights, interface step, block sweeps) from
 inputs already resident in device memory.  Several input/output buffer
 sets are rotated so that consecutive steps do not find their data in the
 256 MB last-level cache.
+
+Other workloads (--workload): `adi` (8192 x 8192 ADI line solves, P = 128)
+and `batch` (256 matrices of uneven sizes and series lengths, one launch
+per step of the method, block counts from the batch autotuner).
 
 Prints one JSON line (see the keys below).  --gpus above 1 is refused: the
 build runs on one GPU.
@@ -25,6 +29,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+F_BYTES = {"f32_refined": 4, "f32_wide": 4, "f32": 4, "f64": 8}
+X_BYTES = {"f32_refined": 8, "f32_wide": 8, "f32": 4, "f64": 8}
+DTYPE = {"f32_refined": "f32+f64", "f64": "f64", "f32_wide": "f32->f64", "f32": "f32"}
+METRIC = "unknowns solved/s + % HBM peak, FP32-refined vs FP64 plain at equal residual"
 
 
 def parse():
@@ -34,9 +42,10 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--mode", default="f32_refined",
                    choices=["f32_refined", "f64", "f32_wide", "f32"])
-    p.add_argument("--workload", default="poisson", choices=["poisson", "adi"],
+    p.add_argument("--workload", default="poisson", choices=["poisson", "adi", "batch"],
                    help="poisson: 1-D Poisson series 4096x4096, P=64 (default); "
-                        "adi: ADI line solves 8192x8192, b=2.05, P=128")
+                        "adi: ADI line solves 8192x8192, b=2.05, P=128; "
+                        "batch: 256 uneven matrices, autotuned block counts")
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
@@ -53,20 +62,19 @@ def parse():
     return p.parse_args()
 
 
-def time_mode(plan, F_sets, X_sets, mode, steps, warmup, torch, graph):
-    """ms per step over `steps` solves (eager launches, or replays of one
-    captured HIP graph per buffer set), then the per-phase split from a
-    separate eager run with the library's phase events on."""
-    n_sets = len(F_sets)
+def time_steps(solve, n_sets, steps, warmup, graph, timed_plan, torch):
+    """ms per step over `steps` calls of solve(k) (eager launches, or replays
+    of one captured HIP graph per buffer set), then the per-phase split from
+    a separate eager run with the library's phase events on."""
     for k in range(max(warmup, n_sets)):
-        plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+        solve(k)
     torch.cuda.synchronize()
+    graphs = []
     if graph:
-        graphs = []
         for k in range(n_sets):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                plan.solve(F_sets[k], X_sets[k], mode=mode)
+                solve(k)
             graphs.append(g)
         for k in range(warmup):
             graphs[k % n_sets].replay()
@@ -74,8 +82,7 @@ def time_mode(plan, F_sets, X_sets, mode, steps, warmup, torch, graph):
         def step(k):
             graphs[k % n_sets].replay()
     else:
-        def step(k):
-            plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+        step = solve
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
@@ -87,19 +94,147 @@ def time_mode(plan, F_sets, X_sets, mode, steps, warmup, torch, graph):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(stop)
-    if graph:
-        del graphs
+    del graphs
     # phase split (events between the launches of each solve)
-    plan.timing(True)
-    plan.timing_read()                 # clear
+    timed_plan.timing(True)
+    timed_plan.timing_read()                 # clear
     for k in range(min(steps, 20)):
-        plan.solve(F_sets[k % n_sets], X_sets[k % n_sets], mode=mode)
+        solve(k)
     torch.cuda.synchronize()
-    ms_beta, ms_iface, ms_sweep, calls = plan.timing_read()
-    plan.timing(False)
+    ms_beta, ms_iface, ms_sweep, calls = timed_plan.timing_read()
+    timed_plan.timing(False)
     return dict(ms_per_step=ms_total / steps, wall_s=wall,
                 ms_beta=ms_beta / calls, ms_iface=ms_iface / calls,
                 ms_sweep=ms_sweep / calls, launch="graph" if graph else "eager")
+
+
+class Single:
+    """One matrix, rotated buffer sets."""
+
+    def __init__(self, args, t, wl, torch):
+        self.args, self.t, self.torch = args, t, torch
+        if args.workload == "poisson":
+            M, N, P = args.M or 4096, args.N or 4096, args.P or 64
+            w = wl.poisson_series(M=M, N=N, P=P)
+            self.name = ("1-D Poisson series (sum of 8 sine modes + noise), FP32 storage with "
+                         "FP64 refinement")
+        else:
+            M, N, P = args.M or 8192, args.N or 8192, args.P or 128
+            w = wl.adi_lines(M=M, N=N, P=P)
+            self.name = ("ADI line solves on a smooth Gaussian random field (b=2.05), "
+                         "FP32 storage")
+        self.M, self.N, self.P = M, N, P
+        self.a, self.b, self.F32 = w["a"], w["b"], w["F"]
+        self.plan = t.Plan(self.a, self.b, P)
+        self.unknowns = M * N
+        self.config = {"workload": self.name, "M": M, "N": N, "P": P}
+
+    def sweep_bytes(self, mode):
+        # the block sweep reads F, writes X, reads two interface values per
+        # block and right-hand side
+        return self.unknowns * (F_BYTES[mode] + X_BYTES[mode]) + 2 * (self.P - 1) * self.N * 8
+
+    def run(self, mode, steps, warmup):
+        torch, args = self.torch, self.args
+        dev = torch.device("cuda:0")
+        per_set = self.unknowns * (F_BYTES[mode] + X_BYTES[mode])
+        n_sets = args.sets or max(1, -(-(512 << 20) // per_set) + 1)
+        Fd = torch.from_numpy(self.F32).to(dev)
+        if F_BYTES[mode] == 8:
+            Fd = Fd.double()
+        xdt = torch.float64 if X_BYTES[mode] == 8 else torch.float32
+        Fs = [Fd] + [Fd.clone() for _ in range(n_sets - 1)]
+        Xs = [torch.empty((self.M, self.N), dtype=xdt, device=dev) for _ in range(n_sets)]
+
+        def solve(k):
+            self.plan.solve(Fs[k % n_sets], Xs[k % n_sets], mode=mode)
+
+        r = time_steps(solve, n_sets, steps, warmup, args.graph, self.plan, torch)
+        eta, r2 = self.plan.residual(Fs[0], Xs[0], mode=mode)
+        torch.cuda.synchronize()
+        r["eta_max"], r["r2_max"], r["sets"] = float(eta.max()), float(r2.max()), n_sets
+        del Fs, Xs
+        torch.cuda.empty_cache()
+        return r
+
+    def cpu_baseline(self, seconds):
+        import numpy as np
+        import oracle
+        Fw = self.F32.astype(np.float64)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.thomas(self.a, self.b, Fw)
+            reps += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        el = time.perf_counter() - t0
+        return {"value": reps * self.unknowns / el, "unit": "unknowns/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"FP64 sequential sweep per RHS (OpenMP over RHS) on the full "
+                          f"{self.M}x{self.N} series, repeated {reps}x over {el:.1f} s"}
+
+
+class Batch:
+    """256 matrices of uneven sizes and series lengths in one batch plan."""
+
+    def __init__(self, args, t, wl, torch):
+        self.args, self.t, self.torch = args, t, torch
+        w = wl.uneven_batch()
+        self.items = w["items"]
+        self.a = [it["a"] for it in self.items]
+        self.b = [it["b"] for it in self.items]
+        self.Ms = [it["M"] for it in self.items]
+        self.Ns = [it["N"] for it in self.items]
+        self.P, self.tune_ms = t.batch_autotune(self.a, self.b, self.Ns, args.mode)
+        self.plan = t.BatchPlan(self.a, self.b, self.P)
+        self.unknowns = sum(m * n for m, n in zip(self.Ms, self.Ns))
+        self.name = ("uneven batch: 256 matrices, M log-uniform [128, 16384], b = 2 + U[0.01, 1], "
+                     "a = -1, N uniform [1, 2048], FP32 storage")
+        self.config = {"workload": self.name, "K": len(self.items), "unknowns": self.unknowns,
+                       "rows_per_block": max(-(-m // p) for m, p in zip(self.Ms, self.P))}
+
+    def sweep_bytes(self, mode):
+        return sum(m * n * (F_BYTES[mode] + X_BYTES[mode]) + 2 * (p - 1) * n * 8
+                   for m, n, p in zip(self.Ms, self.Ns, self.P))
+
+    def run(self, mode, steps, warmup):
+        torch, args = self.torch, self.args
+        dev = torch.device("cuda:0")
+        Fs = []
+        for it in self.items:
+            F = torch.from_numpy(it["F"]).to(dev)
+            Fs.append(F.double() if F_BYTES[mode] == 8 else F)
+        xdt = torch.float64 if X_BYTES[mode] == 8 else torch.float32
+        Xs = [torch.empty((m, n), dtype=xdt, device=dev) for m, n in zip(self.Ms, self.Ns)]
+
+        def solve(k):
+            self.plan.solve(Fs, Xs, mode=mode)
+
+        r = time_steps(solve, 1, steps, warmup, args.graph, self.plan, torch)
+        # residual of the largest series through a single-matrix plan
+        k = max(range(len(self.Ms)), key=lambda i: self.Ms[i] * self.Ns[i])
+        p1 = self.t.Plan(self.a[k], self.b[k], self.P[k])
+        eta, r2 = p1.residual(Fs[k], Xs[k], mode=mode)
+        torch.cuda.synchronize()
+        r["eta_max"], r["r2_max"], r["sets"] = float(eta.max()), float(r2.max()), 1
+        del Fs, Xs
+        torch.cuda.empty_cache()
+        return r
+
+    def cpu_baseline(self, seconds):
+        import numpy as np
+        import oracle
+        done, t0, k = 0, time.perf_counter(), 0
+        while time.perf_counter() - t0 < seconds and k < len(self.items):
+            it = self.items[k]
+            oracle.thomas(it["a"], it["b"], it["F"].astype(np.float64))
+            done += it["M"] * it["N"]
+            k += 1
+        el = time.perf_counter() - t0
+        return {"value": done / el, "unit": "unknowns/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": f"FP64 sequential sweep per RHS on the first {k} of the "
+                          f"{len(self.items)} matrices ({done} unknowns) in {el:.1f} s"}
 
 
 def main():
@@ -108,21 +243,12 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
+    from paper_0901_2859_amd import profdigest
     from paper_0901_2859_amd import tdsolve as t
     from paper_0901_2859_amd import workloads as wl
 
-    if args.workload == "poisson":
-        M, N, P = args.M or 4096, args.N or 4096, args.P or 64
-        w = wl.poisson_series(M=M, N=N, P=P)
-        wname = "1-D Poisson series (sum of 8 sine modes + noise), FP32 storage with FP64 refinement"
-    else:
-        M, N, P = args.M or 8192, args.N or 8192, args.P or 128
-        w = wl.adi_lines(M=M, N=N, P=P)
-        wname = "ADI line solves on a smooth Gaussian random field (b=2.05), FP32 storage"
-    a, b, F32 = w["a"], w["b"], w["F"]
     dev = torch.device("cuda:0")
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
@@ -131,50 +257,29 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    plan = t.Plan(a, b, P)
 
-    f_bytes = {"f32_refined": 4, "f32_wide": 4, "f32": 4, "f64": 8}
-    x_bytes = {"f32_refined": 8, "f32_wide": 8, "f32": 4, "f64": 8}
-
-    def make_sets(mode):
-        per_set = M * N * (f_bytes[mode] + x_bytes[mode])
-        n_sets = args.sets or max(1, -(-(512 << 20) // per_set) + 1)
-        Fd = torch.from_numpy(F32).to(dev)
-        if f_bytes[mode] == 8:
-            Fd = Fd.double()
-        xdt = torch.float64 if x_bytes[mode] == 8 else torch.float32
-        Fs = [Fd] + [Fd.clone() for _ in range(n_sets - 1)]
-        Xs = [torch.empty((M, N), dtype=xdt, device=dev) for _ in range(n_sets)]
-        return Fs, Xs
+    W = (Batch if args.workload == "batch" else Single)(args, t, wl, torch)
 
     def run(mode, steps, warmup):
-        Fs, Xs = make_sets(mode)
-        r = time_mode(plan, Fs, Xs, mode, steps, warmup, torch, args.graph)
-        eta, r2 = plan.residual(Fs[0], Xs[0], mode=mode)
-        torch.cuda.synchronize()
-        r["eta_max"] = float(eta.max())
-        r["r2_max"] = float(r2.max())
-        r["sets"] = len(Fs)
-        r["unknowns_per_s"] = M * N / (r["ms_per_step"] * 1e-3)
-        alg = M * N * (f_bytes[mode] + x_bytes[mode])
+        r = W.run(mode, steps, warmup)
+        r["unknowns_per_s"] = W.unknowns / (r["ms_per_step"] * 1e-3)
+        alg = W.unknowns * (F_BYTES[mode] + X_BYTES[mode])
         r["path_gbs"] = alg / (r["ms_per_step"] * 1e-3) / 1e9
-        del Fs, Xs
-        torch.cuda.empty_cache()
         return r
 
     main_r = run(args.mode, args.steps, args.warmup)
 
-    # dominant kernel: the block sweep (reads F, writes X, reads two
-    # interface values per block and right-hand side)
-    sweep_bytes = M * N * (f_bytes[args.mode] + x_bytes[args.mode]) + 2 * (P - 1) * N * 8
+    # dominant kernel: the block sweep
+    sweep_bytes = W.sweep_bytes(args.mode)
     ms_sweep = main_r["ms_sweep"]
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
-    kname = "k_sweep_reg"
+    kname = "k_sweep_batch" if args.workload == "batch" else "k_sweep_reg"
+    shape = ("batch" if args.workload == "batch"
+             else f"{args.workload}_{W.M}x{W.N}_P{W.P}")
     # HBM bytes per launch measured by rocprofv3 counters for this kernel,
     # mode and workload; null unless taken from the current kernel sources
-    from paper_0901_2859_amd import profdigest
     tr = profdigest.read_traffic(os.path.join(
-        ROOT, "profiles", f"{kname}_{args.mode}_{args.workload}_{M}x{N}_P{P}_traffic.txt"))
+        ROOT, "profiles", f"{kname}_{args.mode}_{shape}_traffic.txt"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tr is None else round(tr[0]),
@@ -186,27 +291,12 @@ def main():
         for mode in ("f64", "f32_wide"):
             if mode == args.mode:
                 continue
-            r = run(mode, max(10, args.steps // 2), max(3, args.warmup // 2))
-            compare[mode] = r
+            compare[mode] = run(mode, max(10, args.steps // 2), max(3, args.warmup // 2))
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        Fw = F32.astype(np.float64)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            oracle.thomas(a, b, Fw)
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        el = time.perf_counter() - t0
-        cpu = {"value": reps * M * N / el, "unit": "unknowns/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"FP64 sequential sweep per RHS (OpenMP over RHS) on the full "
-                         f"{M}x{N} Poisson series, repeated {reps}x over {el:.1f} s"}
+    cpu = None if args.no_cpu else W.cpu_baseline(args.cpu_seconds)
 
     out = {
-        "metric": "unknowns solved/s + % HBM peak, FP32-refined vs FP64 plain at equal residual",
+        "metric": METRIC,
         "value": main_r["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
@@ -216,14 +306,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32_refined": "f32+f64", "f64": "f64", "f32_wide": "f32->f64", "f32": "f32"}[args.mode],
+        "dtype": DTYPE[args.mode],
         "data": "synthetic",
-        "config": {"workload": wname, "M": M, "N": N, "P": P,
-                   "mode": args.mode, "layout": "RHS-interleaved [M][N]",
-                   "buffer_sets": main_r["sets"], "launch": main_r["launch"]},
+        "config": dict(W.config, mode=args.mode, layout="RHS-interleaved [M][N]",
+                       buffer_sets=main_r["sets"], launch=main_r["launch"]),
         "hbm_frac_path": round(main_r["path_gbs"] / HBM_PEAK_GBS, 4),
         "path_gbs": round(main_r["path_gbs"], 1),
-        "phases_ms": {"beta_interface": round(main_r["ms_beta"] + main_r["ms_iface"], 5),
+        "phases_ms": {"beta": round(main_r["ms_beta"], 5),
+                      "interface": round(main_r["ms_iface"], 5),
                       "sweep": round(main_r["ms_sweep"], 5)},
         "r2_max": main_r["r2_max"],
         "eta_max": main_r["eta_max"],

@@ -160,6 +160,21 @@ int tdsolve_prepare_host(const double* a, const double* b, int64_t M,
 /* Block count the library would choose for P == 0. */
 int32_t tdsolve_default_blocks(int64_t M);
 
+/* Measured block count.  The split into P blocks is free in the method
+ * (Algorithm 3 holds for any P with blocks of >= 2 rows); it trades the
+ * interface work per right-hand side, which grows with P, against the
+ * block sweeps, whose register footprint grows with the rows per block.
+ * Times tdsolve_series for blocks of at most 16, 32, 64 and 128 rows (and
+ * P = 1 when M <= 128) on N device-generated uniform[-1, 1) right-hand
+ * sides in `mode`, `reps` timed calls each (<= 0: 5), and writes the
+ * fastest P to *P_out and its milliseconds per call to *ms_out (may be
+ * NULL).  a, b as for tdsolve_prepare.  Allocates and frees device memory
+ * and synchronises `stream`.  Errors: as tdsolve_prepare, TDS_EINVAL for
+ * N < 1 or a bad mode, TDS_ENOMEM, TDS_EHIP. */
+int tdsolve_autotune(const double* a, const double* b, int64_t M, int64_t N,
+                     int32_t mode, int32_t reps, int32_t* P_out, double* ms_out,
+                     void* stream);
+
 int tdsolve_destroy(tds_handle h);
 
 const char* tdsolve_strerror(int code);
@@ -178,6 +193,18 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a,
  * series are solved by one launch of each kernel. */
 int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
                          const int64_t* N, int32_t mode, void* stream);
+
+/* Measured block counts for a batch.  The batch kernels hold every block
+ * in one common register row bucket, so the choice is the rows per block,
+ * 32 or 64, shared by all matrices (P[k] = ceil(M[k] / rows) within the
+ * method's limits); each choice is timed on tdsolve_batch_series with N[k]
+ * device-generated right-hand sides, and the fastest P[k] are written to
+ * P_out (K entries), the milliseconds per call to *ms_out (may be NULL).
+ * Allocation, synchronisation and errors as tdsolve_autotune. */
+int tdsolve_batch_autotune(int32_t K, const double* const* a,
+                           const double* const* b, const int64_t* M,
+                           const int64_t* N, int32_t mode, int32_t reps,
+                           int32_t* P_out, double* ms_out, void* stream);
 
 #ifdef __cplusplus
 }

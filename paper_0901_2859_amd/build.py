@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdsolve.so")
-SOURCES = ["tds_kernels.hip", "tds_aux.hip", "tds_api.cpp", "tds_prepare.cpp"]
+SOURCES = ["tds_kernels.hip", "tds_aux.hip", "tds_api.cpp", "tds_prepare.cpp", "tds_autotune.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

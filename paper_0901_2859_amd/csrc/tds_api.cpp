@@ -543,9 +543,12 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
             return TDS_EHIP;
         h->desc = desc;
     }
-    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes,
+    hipEvent_t* ev = timing_slot(h);
+    if (ev && hipEventRecord(ev[0], (hipStream_t)stream) != hipSuccess) return TDS_EHIP;
+    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, ev,
                      (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
+    if (ev && hipEventRecord(ev[3], (hipStream_t)stream) != hipSuccess) return TDS_EHIP;
     return TDS_OK;
 }
 

@@ -2,6 +2,8 @@
 // metrics of a computed solution and the reductions of the adjoint
 // (gradients with respect to the matrix coefficients).
 #include "tdsolve.h"
+#include <algorithm>
+
 #include "tds_internal.h"
 
 namespace tds {
@@ -148,6 +150,31 @@ hipError_t launch_adjoint_reduce(const DevTables& t, const void* X, const void* 
     else
         hipLaunchKernelGGL((k_adjoint_reduce<float, double>), g, dim3(kWG), 0, s,
                            (const float*)X, (const double*)gF, N, t.M, ga, gb);
+    return hipGetLastError();
+}
+
+// Counter-based uniform[-1, 1) fill (splitmix64 of the element index and a
+// seed) for timing runs that need right-hand sides but no host data.
+template <typename T>
+__global__ void k_fill_uniform(T* __restrict__ p, int64_t n, uint64_t seed) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        p[i] = (T)((double)(z >> 11) * 0x1.0p-52 - 1.0);
+    }
+}
+
+hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + kWG - 1) / kWG, 8192);
+    if (f32)
+        hipLaunchKernelGGL(k_fill_uniform<float>, dim3(blocks), dim3(kWG), 0, s, (float*)p, n, seed);
+    else
+        hipLaunchKernelGGL(k_fill_uniform<double>, dim3(blocks), dim3(kWG), 0, s, (double*)p, n,
+                           seed);
     return hipGetLastError();
 }
 

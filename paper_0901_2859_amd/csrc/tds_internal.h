@@ -102,10 +102,14 @@ struct BatchDesc {
 
 // The three steps for all matrices of a batch: one launch each.  `bucket`
 // is the common register-sweep row bucket (32 or 64).
+// `ev` (may be null): events [1] and [2] are recorded after the beta and
+// interface launches.
 hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items,
                         int64_t scans, int32_t bucket, int mode, int passes,
-                        hipStream_t s);
+                        hipEvent_t* ev, hipStream_t s);
 
+// uniform[-1, 1) values from a counter-based generator (timing inputs)
+hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipStream_t s);
 hipError_t launch_residual(const DevTables& t, const void* F, const void* X,
                            int64_t N, int mode, double normA, double* part,
                            double* out, hipStream_t s);

@@ -688,7 +688,7 @@ static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, 
 }
 
 hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t scans,
-                        int32_t bucket, int mode, int passes, hipStream_t s) {
+                        int32_t bucket, int mode, int passes, hipEvent_t* ev, hipStream_t s) {
     if (items == 0) return hipSuccess;
     if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
     if (items > INT32_MAX / kBetaWaves) return hipErrorInvalidValue;
@@ -707,12 +707,14 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (scans > 0) {
         hipLaunchKernelGGL(k_iface_batch, dim3((unsigned)scans), dim3(kScanRhs * kScanMaxGroups),
                            0, s, D, K);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     if (bucket == 32)
         batch_sweep<32>(D, K, items, mode, passes, s);
     else

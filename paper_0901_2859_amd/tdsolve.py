@@ -11,6 +11,8 @@ whose column n is right-hand side n (row-major, contiguous).
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
 import os
 from typing import Optional
 
@@ -28,7 +30,7 @@ SYMBOLS = [
     "tdsolve_residual", "tdsolve_set_refinement", "tdsolve_info", "tdsolve_prepare_host",
     "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
-    "tdsolve_timing_read",
+    "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
 ]
 
 _lib = None
@@ -74,6 +76,8 @@ def lib():
     L.tdsolve_batch_series.argtypes = [vp, vp, vp, vp, i32, vp]
     L.tdsolve_timing_enable.argtypes = [vp, i32]
     L.tdsolve_timing_read.argtypes = [vp, vp, vp]
+    L.tdsolve_autotune.argtypes = [dp, dp, i64, i64, i32, i32, vp, vp, vp]
+    L.tdsolve_batch_autotune.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("tdsolve_default_blocks", "tdsolve_strerror"):
             getattr(L, name).restype = ctypes.c_int
@@ -269,6 +273,16 @@ class BatchPlan:
         self._h = h
         self.K = K
 
+    def timing(self, on: bool = True):
+        _check(lib().tdsolve_timing_enable(self._h, int(bool(on))), "tdsolve_timing_enable")
+
+    def timing_read(self):
+        """(ms_beta, ms_interface, ms_sweep, calls) accumulated since the last read."""
+        ms = np.zeros(3)
+        calls = np.zeros(1, dtype=np.int64)
+        _check(lib().tdsolve_timing_read(self._h, _ptr(ms), _ptr(calls)), "tdsolve_timing_read")
+        return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
+
     def solve(self, F_list, X_list=None, mode="f32_refined", stream=None):
         import torch
         m = mode_id(mode)
@@ -304,6 +318,96 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def _cache_path():
+    return os.environ.get("TDSOLVE_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "tdsolve",
+                                       "autotune.json"))
+
+
+def _device_key():
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{getattr(p, 'gcnArchName', p.name)}:{p.multi_processor_count}"
+
+
+def _cache_load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _cache_store(key, value):
+    path = _cache_path()
+    data = _cache_load()
+    data[key] = value
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass                     # an unwritable cache only costs a re-measurement
+
+
+def autotune(a, b, N: int, mode="f32_refined", reps: int = 5, cache: bool = True,
+             stream=None):
+    """Block count P for solving series of N right-hand sides with the
+    tridiagonal matrix (a, b) in `mode`, measured on the current device by
+    tdsolve_autotune (fastest of blocks of <= 16/32/64/128 rows).  Results
+    are cached in a JSON file (TDSOLVE_AUTOTUNE_CACHE, default
+    ~/.cache/tdsolve/autotune.json) by device, M, N and mode: the timing
+    does not depend on the matrix values.  Returns (P, ms per solve)."""
+    m = mode_id(mode)
+    b = _host_f64(b)
+    M = int(b.shape[0])
+    a = _host_f64(a) if M > 1 else np.zeros(1)
+    key = f"single|{_device_key()}|M={M}|N={int(N)}|mode={m}"
+    if cache:
+        hit = _cache_load().get(key)
+        if hit is not None:
+            return int(hit["P"]), float(hit["ms"])
+    P = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(lib().tdsolve_autotune(_ptr(a), _ptr(b), M, int(N), m, int(reps), ctypes.byref(P),
+                                  ctypes.byref(ms), _stream_ptr(stream)), "tdsolve_autotune")
+    if cache:
+        _cache_store(key, {"P": P.value, "ms": ms.value})
+    return P.value, ms.value
+
+
+def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
+                   cache: bool = True, stream=None):
+    """Block counts for an uneven batch (tdsolve_batch_autotune: one shared
+    choice of 32 or 64 rows per block, timed on the whole batch).  Cached
+    like autotune(), by device, mode and the digest of the (M, N) list.
+    Returns (list of P, ms per batch solve)."""
+    m = mode_id(mode)
+    K = len(b_list)
+    bs = [_host_f64(b) for b in b_list]
+    as_ = [(_host_f64(a) if len(b) > 1 else np.zeros(1)) for a, b in zip(a_list, bs)]
+    Ms = np.array([x.shape[0] for x in bs], dtype=np.int64)
+    Ns = np.array([int(n) for n in N_list], dtype=np.int64)
+    digest = hashlib.sha256(Ms.tobytes() + Ns.tobytes()).hexdigest()[:16]
+    key = f"batch|{_device_key()}|K={K}|MN={digest}|mode={m}"
+    if cache:
+        hit = _cache_load().get(key)
+        if hit is not None:
+            return [int(p) for p in hit["P"]], float(hit["ms"])
+    ap = (ctypes.c_void_p * K)(*[x.ctypes.data for x in as_])
+    bp = (ctypes.c_void_p * K)(*[x.ctypes.data for x in bs])
+    Ps = np.zeros(K, dtype=np.int32)
+    ms = ctypes.c_double()
+    _check(lib().tdsolve_batch_autotune(K, ap, bp, _ptr(Ms), _ptr(Ns), m, int(reps), _ptr(Ps),
+                                        ctypes.byref(ms), _stream_ptr(stream)),
+           "tdsolve_batch_autotune")
+    if cache:
+        _cache_store(key, {"P": Ps.tolist(), "ms": ms.value})
+    return Ps.tolist(), ms.value
 
 
 def _autograd_fn():

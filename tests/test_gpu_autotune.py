@@ -1,0 +1,84 @@
+"""GPU: the measured block-count choice (tdsolve_autotune,
+tdsolve_batch_autotune) and its JSON cache.  The chosen decomposition is a
+free parameter of the method, so the checks are that the choice is one of
+the candidates, that a plan built with it solves to the oracle's tolerance,
+and that the cache returns the stored choice without measuring again."""
+import json
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_0901_2859_amd import tdsolve as t  # noqa: E402
+from paper_0901_2859_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _candidates(M):
+    out = set()
+    for rows in (16, 32, 64, 128):
+        P = 1 if M < 4 else max(1, min(-(-M // rows), M // 2, 65535))
+        out.add(P)
+    if M <= 128:
+        out.add(1)
+    return out
+
+
+@pytest.mark.parametrize("M,N,mode", [(4096, 512, "f32_refined"), (1000, 300, "f64"),
+                                      (100, 17, "f32_wide")])
+def test_autotune_choice_solves(M, N, mode, tmp_path, monkeypatch):
+    monkeypatch.setenv("TDSOLVE_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    rng = np.random.default_rng(M + N)
+    a = -rng.uniform(0.5, 1.0, size=M - 1)
+    b = 2.2 + rng.uniform(0.0, 1.0, size=M)
+    P, ms = t.autotune(a, b, N, mode)
+    print(f"autotune M={M} N={N} mode={mode}: P={P} {ms:.4f} ms", flush=True)
+    assert P in _candidates(M) and ms > 0
+    F = rng.uniform(-1, 1, size=(M, N))
+    Fin = torch.from_numpy(F if mode == "f64" else F.astype(np.float32)).to(DEV)
+    X = t.Plan(a, b, P).solve(Fin, mode=mode).cpu().numpy()
+    ref = oracle.thomas(a, b, Fin.cpu().double().numpy())
+    assert np.max(np.abs(X - ref)) <= 1e-11 * np.max(np.abs(ref))
+    # second call: answered from the cache file
+    data = json.loads((tmp_path / "cache.json").read_text())
+    assert any(v["P"] == P for v in data.values())
+    key = next(iter(data))
+    data[key]["P"] = 1            # a value measurement could not give here
+    (tmp_path / "cache.json").write_text(json.dumps(data))
+    if M > 128:
+        assert t.autotune(a, b, N, mode)[0] == 1
+        assert t.autotune(a, b, N, mode, cache=False)[0] in _candidates(M)
+
+
+def test_batch_autotune_choice_solves(tmp_path, monkeypatch):
+    monkeypatch.setenv("TDSOLVE_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    w = wl.uneven_batch(seed=9, K=12, M_lo=64, M_hi=3000, N_hi=600)
+    items = w["items"]
+    a_l, b_l = [it["a"] for it in items], [it["b"] for it in items]
+    P_l, ms = t.batch_autotune(a_l, b_l, [it["N"] for it in items], "f32_refined")
+    assert ms > 0 and len(P_l) == len(items)
+    rows = {32, 64}
+    ok = [r for r in rows
+          if all(P == (1 if it["M"] < 4 else max(1, min(-(-it["M"] // r), it["M"] // 2)))
+                 for P, it in zip(P_l, items))]
+    assert ok, P_l
+    bp = t.BatchPlan(a_l, b_l, P_l)
+    Xs = bp.solve([torch.from_numpy(it["F"]).to(DEV) for it in items], mode="f32_refined")
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        ref = oracle.thomas(it["a"], it["b"], it["F"].astype(np.float64))
+        X = Xs[k].cpu().numpy()
+        assert np.max(np.abs(X - ref)) <= 1e-11 * np.max(np.abs(ref)), k
+    assert t.batch_autotune(a_l, b_l, [it["N"] for it in items], "f32_refined")[0] == P_l
+
+
+def test_autotune_rejects_bad_arguments():
+    a, b = -np.ones(9), 3 * np.ones(10)
+    with pytest.raises(t.TdsError):
+        t.autotune(a, b, 0, "f64", cache=False)
+    with pytest.raises(t.TdsError):
+        t.autotune(a, b, 4, 7, cache=False)

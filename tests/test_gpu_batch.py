@@ -108,3 +108,24 @@ def test_batch_graph_replays():
         for X, R in zip(Xs, ref):
             assert torch.equal(X, R), rep
         _ = (Fs[0] * 2).sum().item()                   # eager work between replays
+
+
+def test_uneven_batch_full_size_sampled(tmp_path, monkeypatch):
+    # the full uneven batch (256 matrices, M log-uniform in [128, 16384],
+    # N uniform in [1, 2048], FP32 storage with refinement) with the batch
+    # autotuner's block counts, in the launch configuration the benchmark
+    # times; the first, middle and last right-hand side of every matrix
+    # against the oracle
+    monkeypatch.setenv("TDSOLVE_AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
+    items = wl.uneven_batch()["items"]
+    a_l, b_l = [it["a"] for it in items], [it["b"] for it in items]
+    P_l, ms = t.batch_autotune(a_l, b_l, [it["N"] for it in items], "f32_refined")
+    print(f"full batch: {sum(it['M'] * it['N'] for it in items)} unknowns, {ms:.3f} ms",
+          flush=True)
+    bp = t.BatchPlan(a_l, b_l, P_l)
+    Xs = bp.solve([torch.from_numpy(it["F"]).to(DEV) for it in items], mode="f32_refined")
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        cols = sorted({0, it["N"] // 2, it["N"] - 1})
+        X = Xs[k][:, cols].cpu().numpy()
+        _check(it["a"], it["b"], it["F"][:, cols].astype(np.float64), X, P_l[k])
