@@ -9,9 +9,12 @@ inputs already resident in device memory.  Several input/output buffer
 sets are rotated so that consecutive steps do not find their data in the
 256 MB last-level cache.
 
-Other workloads (--workload): `adi` (8192 x 8192 ADI line solves, P = 128)
-and `batch` (256 matrices of uneven sizes and series lengths, one launch
-per step of the method, block counts from the batch autotuner).
+Other workloads (--workload): `adi` (8192 x 8192 ADI line solves, P = 128),
+`batch` (256 matrices of uneven sizes and series lengths, one launch per
+step of the method, block counts from the batch autotuner) and `gradient`
+(2048 x 1024, one step = forward solve + adjoint: gF, ga, gb).  The
+preliminary step (host FP64 tables + upload) is timed separately
+(`prepare_ms`).
 
 Prints one JSON line (see the keys below).  --gpus above 1 is refused: the
 build runs on one GPU.
@@ -42,10 +45,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--mode", default="f32_refined",
                    choices=["f32_refined", "f64", "f32_wide", "f32"])
-    p.add_argument("--workload", default="poisson", choices=["poisson", "adi", "batch"],
+    p.add_argument("--workload", default="poisson",
+                   choices=["poisson", "adi", "batch", "gradient"],
                    help="poisson: 1-D Poisson series 4096x4096, P=64 (default); "
                         "adi: ADI line solves 8192x8192, b=2.05, P=128; "
-                        "batch: 256 uneven matrices, autotuned block counts")
+                        "batch: 256 uneven matrices, autotuned block counts; "
+                        "gradient: 2048x1024 forward + adjoint, P=32")
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
@@ -125,7 +130,10 @@ class Single:
                          "FP32 storage")
         self.M, self.N, self.P = M, N, P
         self.a, self.b, self.F32 = w["a"], w["b"], w["F"]
+        t0 = time.perf_counter()
         self.plan = t.Plan(self.a, self.b, P)
+        torch.cuda.synchronize()
+        self.prepare_ms = (time.perf_counter() - t0) * 1e3
         self.unknowns = M * N
         self.config = {"workload": self.name, "M": M, "N": N, "P": P}
 
@@ -186,7 +194,10 @@ class Batch:
         self.Ms = [it["M"] for it in self.items]
         self.Ns = [it["N"] for it in self.items]
         self.P, self.tune_ms = t.batch_autotune(self.a, self.b, self.Ns, args.mode)
+        t0 = time.perf_counter()
         self.plan = t.BatchPlan(self.a, self.b, self.P)
+        torch.cuda.synchronize()
+        self.prepare_ms = (time.perf_counter() - t0) * 1e3
         self.unknowns = sum(m * n for m, n in zip(self.Ms, self.Ns))
         self.name = ("uneven batch: 256 matrices, M log-uniform [128, 16384], b = 2 + U[0.01, 1], "
                      "a = -1, N uniform [1, 2048], FP32 storage")
@@ -237,6 +248,45 @@ class Batch:
                           f"{len(self.items)} matrices ({done} unknowns) in {el:.1f} s"}
 
 
+class Gradient(Single):
+    """Forward solve and adjoint of loss = sum(W * X): one step computes X,
+    then gF = A^{-1} W and the reductions ga, gb with the same plan."""
+
+    def __init__(self, args, t, wl, torch):
+        self.args, self.t, self.torch = args, t, torch
+        w = wl.gradient_case()
+        self.M, self.N, self.P = w["M"], w["N"], w["P"]
+        self.a, self.b, self.F32, self.W = w["a"], w["b"], w["F"], w["W"]
+        t0 = time.perf_counter()
+        self.plan = t.Plan(self.a, self.b, self.P)
+        torch.cuda.synchronize()
+        self.prepare_ms = (time.perf_counter() - t0) * 1e3
+        self.unknowns = self.M * self.N
+        self.name = ("differentiation: b = 3 + U[0, 1], a ~ U[-1, -0.5], FP32 storage, "
+                     "forward + adjoint (gF, ga, gb) per step")
+        self.config = {"workload": self.name, "M": self.M, "N": self.N, "P": self.P}
+
+    def run(self, mode, steps, warmup):
+        torch = self.torch
+        dev = torch.device("cuda:0")
+        F = torch.from_numpy(self.F32).to(dev)
+        if F_BYTES[mode] == 8:
+            F = F.double()
+        xdt = torch.float64 if X_BYTES[mode] == 8 else torch.float32
+        X = torch.empty((self.M, self.N), dtype=xdt, device=dev)
+        W = torch.from_numpy(self.W).to(dev).to(xdt)
+
+        def solve(k):
+            self.plan.solve(F, X, mode=mode)
+            self.plan.backward(X, W, mode=mode)
+
+        r = time_steps(solve, 1, steps, warmup, self.args.graph, self.plan, torch)
+        eta, r2 = self.plan.residual(F, X, mode=mode)
+        torch.cuda.synchronize()
+        r["eta_max"], r["r2_max"], r["sets"] = float(eta.max()), float(r2.max()), 1
+        return r
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,7 +308,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    W = (Batch if args.workload == "batch" else Single)(args, t, wl, torch)
+    W = {"batch": Batch, "gradient": Gradient}.get(args.workload, Single)(args, t, wl, torch)
 
     def run(mode, steps, warmup):
         r = W.run(mode, steps, warmup)
@@ -317,6 +367,7 @@ def main():
                       "sweep": round(main_r["ms_sweep"], 5)},
         "r2_max": main_r["r2_max"],
         "eta_max": main_r["eta_max"],
+        "prepare_ms": round(W.prepare_ms, 3),
         "roofline": roofline,
         "compare": compare,
         "cpu_baseline": cpu,
