@@ -85,6 +85,7 @@ typedef struct {
     int32_t refine_passes;/* passes used by TDS_F32_REFINED */
     double max_ratio;     /* max |Z_{k+1}/Z_k| over both sweeps; <= 1 under
                              dominance (proof of Theorem 4) */
+    int32_t general;      /* 1 for a plan of tdsolve_prepare_general */
 } tds_info;
 
 /* Preliminary step (Algorithm 3 step 1).  a: M-1 host doubles (may be NULL
@@ -96,6 +97,22 @@ typedef struct {
  * TDS_ENOMEM, TDS_EHIP (device upload). */
 int tdsolve_prepare(const double* a, const double* b, int64_t M, int32_t P,
                     tds_handle* out);
+
+/* Preliminary step for a non-symmetric tridiagonal A (section
+ * "Nonsymmetrical matrices"): row i reads lower[i-1] x_{i-1} + diag[i] x_i +
+ * upper[i] x_{i+1} (lower, upper: M-1 host doubles, A[i+1][i] = lower[i],
+ * A[i][i+1] = upper[i]; NULL allowed when M == 1).  Requires
+ * lower[i] * upper[i] > 0 for every i: then the diagonal similarity
+ * D^{-1} A D with d_{i+1} / d_i = sqrt(lower[i] / upper[i]) is symmetric and
+ * the symmetric preliminary step applies to it; the weights and transfer
+ * factors are mapped back to A, and the block sweeps run on A itself, so
+ * tdsolve_series, tdsolve_components and tdsolve_residual work unchanged.
+ * tdsolve_backward returns TDS_EUNSUPPORTED for such a plan (its adjoint
+ * solves with A^T).  Errors: as tdsolve_prepare, and TDS_EUNSUPPORTED when
+ * some lower[i] * upper[i] <= 0. */
+int tdsolve_prepare_general(const double* lower, const double* diag,
+                            const double* upper, int64_t M, int32_t P,
+                            tds_handle* out);
 
 /* Solve the series (Algorithm 1 with Algorithm 3 step 2 for the interface
  * rows).  F: device [M][N] (double for TDS_F64, float otherwise).
@@ -156,6 +173,14 @@ int tdsolve_info(tds_handle h, tds_info* info);
 int tdsolve_prepare_host(const double* a, const double* b, int64_t M,
                          int32_t P, int64_t* starts, double* wR, double* wL,
                          double* rho, double* lam, double* diag_inv);
+
+/* The same tables for a non-symmetric A (as tdsolve_prepare_general):
+ * wR, wL are rows of A^{-1} at the interface rows, rho, lam the transfer
+ * factors of the solution between neighbouring interface rows. */
+int tdsolve_prepare_host_general(const double* lower, const double* diag,
+                                 const double* upper, int64_t M, int32_t P,
+                                 int64_t* starts, double* wR, double* wL,
+                                 double* rho, double* lam, double* diag_inv);
 
 /* Block count the library would choose for P == 0. */
 int32_t tdsolve_default_blocks(int64_t M);

@@ -54,6 +54,8 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     const size_t o_wR = take(sizeof(double) * MR), o_wL = take(sizeof(double) * MR);
     const size_t o_rho = take(sizeof(double) * P), o_lam = take(sizeof(double) * P);
     const size_t o_a64 = take(sizeof(double) * MR), o_b64 = take(sizeof(double) * MR);
+    const size_t o_l64 = take(sizeof(double) * MR), o_inl64 = take(sizeof(double) * MR);
+    const size_t o_l32 = take(sizeof(float) * MR), o_inl32 = take(sizeof(float) * MR);
     const size_t o_cp64 = take(sizeof(double) * MR), o_rd64 = take(sizeof(double) * MR);
     const size_t o_wpad = take(sizeof(double) * 2 * (size_t)P * (size_t)(WP > 0 ? WP : 1));
     const size_t o_in64 = take(sizeof(double) * MR), o_u = take(sizeof(double) * MR);
@@ -94,9 +96,16 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
             }
         put(o_wpad, wp.data(), sizeof(double) * wp.size());
     }
-    std::vector<double> in(o.a64);
-    for (int32_t j = 0; j < P; ++j) in[o.starts[j + 1] - 1] = 0.0;   // block ends
+    std::vector<double> in(o.a64), inl(o.l64);
+    for (int32_t j = 0; j < P; ++j) {                                 // block ends
+        in[o.starts[j + 1] - 1] = 0.0;
+        inl[o.starts[j + 1] - 1] = 0.0;
+    }
     pad64(o_in64, in, 0.0);
+    pad64(o_l64, o.l64, 0.0);
+    pad64(o_inl64, inl, 0.0);
+    pad32(o_l32, o.l64, 0.0f);
+    pad32(o_inl32, inl, 0.0f);
     pad64(o_u, o.u, 0.0);
     pad64(o_v, o.v, 0.0);
     pad32(o_a32, o.a64, 0.0f);
@@ -113,7 +122,12 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     d.wL = (double*)o_wL;
     d.rho = (double*)o_rho;
     d.lam = (double*)o_lam;
+    d.general = o.general;
     d.a64 = (double*)o_a64;
+    d.l64 = (double*)o_l64;
+    d.inl64 = (double*)o_inl64;
+    d.l32 = (float*)o_l32;
+    d.inl32 = (float*)o_inl32;
     d.b64 = (double*)o_b64;
     d.cp64 = (double*)o_cp64;
     d.rd64 = (double*)o_rd64;
@@ -140,6 +154,7 @@ void rebase(DevTables& d, void* mem) {
     shift(d.a64, b); shift(d.b64, b); shift(d.cp64, b); shift(d.rd64, b); shift(d.wpad, b);
     shift(d.in64, b); shift(d.u, b); shift(d.v, b); shift(d.a32, b); shift(d.cp32, b);
     shift(d.rd32, b); shift(d.in32, b);
+    shift(d.l64, b); shift(d.inl64, b); shift(d.l32, b); shift(d.inl32, b);
 }
 
 int upload_image(const std::vector<unsigned char>& img, void** out) {
@@ -266,6 +281,23 @@ hipError_t zero_f64(double* p, int64_t n, hipStream_t s) {
 
 extern "C" {
 
+// checks, ||A||_inf and upload after the host tables are in place
+static int finish_plan(tds_plan* h, tds_handle* out) {
+    if (h->host.P > 65535) { delete h; return TDS_EUNSUPPORTED; }
+    const int64_t M = h->host.M;
+    double normA = 0.0;
+    for (int64_t i = 0; i < M; ++i) {
+        double r = fabs(h->host.b64[i]) + (i > 0 ? fabs(h->host.l64[i - 1]) : 0.0) +
+                   fabs(h->host.a64[i]);
+        normA = std::max(normA, r);
+    }
+    h->normA = normA;
+    const int rc = upload(h);
+    if (rc) { delete h; return rc; }
+    *out = h;
+    return TDS_OK;
+}
+
 int tdsolve_prepare(const double* a, const double* b, int64_t M, int32_t P, tds_handle* out) {
     if (!out) return TDS_EINVAL;
     *out = nullptr;
@@ -273,18 +305,18 @@ int tdsolve_prepare(const double* a, const double* b, int64_t M, int32_t P, tds_
     if (!h) return TDS_ENOMEM;
     int rc = host_prepare(a, b, M, P, h->host);
     if (rc) { delete h; return rc; }
-    if (h->host.P > 65535) { delete h; return TDS_EUNSUPPORTED; }
-    double normA = 0.0;
-    for (int64_t i = 0; i < M; ++i) {
-        double r = fabs(h->host.b64[i]) + (i > 0 ? fabs(h->host.a64[i - 1]) : 0.0) +
-                   fabs(h->host.a64[i]);
-        normA = std::max(normA, r);
-    }
-    h->normA = normA;
-    rc = upload(h);
+    return finish_plan(h, out);
+}
+
+int tdsolve_prepare_general(const double* lower, const double* diag, const double* upper,
+                            int64_t M, int32_t P, tds_handle* out) {
+    if (!out) return TDS_EINVAL;
+    *out = nullptr;
+    tds_plan* h = new (std::nothrow) tds_plan();
+    if (!h) return TDS_ENOMEM;
+    int rc = host_prepare_general(lower, diag, upper, M, P, h->host);
     if (rc) { delete h; return rc; }
-    *out = h;
-    return TDS_OK;
+    return finish_plan(h, out);
 }
 
 int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N, int32_t mode, void* stream) {
@@ -314,6 +346,7 @@ int tdsolve_backward(tds_handle h, const void* X, const void* gX, void* gF, doub
                      double* gb, int64_t N, int32_t mode, void* stream) {
     int rc = check_common(h, N, mode);
     if (rc) return rc;
+    if (h->host.general) return TDS_EUNSUPPORTED;     // the adjoint solves with A^T
     if (N == 0) {
         hipStream_t s = (hipStream_t)stream;
         if (zero_f64(ga, h->dev.M - 1, s) != hipSuccess) return TDS_EHIP;
@@ -408,6 +441,7 @@ int tdsolve_info(tds_handle h, tds_info* info) {
     info->dominant = h->host.dominant;
     info->refine_passes = h->passes;
     info->max_ratio = h->host.max_ratio;
+    info->general = h->host.general;
     return TDS_OK;
 }
 
@@ -415,6 +449,21 @@ int tdsolve_prepare_host(const double* a, const double* b, int64_t M, int32_t P,
                          double* wR, double* wL, double* rho, double* lam, double* diag_inv) {
     HostTables o;
     int rc = host_prepare(a, b, M, P, o);
+    if (rc) return rc;
+    if (starts) memcpy(starts, o.starts.data(), sizeof(int64_t) * (o.P + 1));
+    if (wR) memcpy(wR, o.wR.data(), sizeof(double) * M);
+    if (wL) memcpy(wL, o.wL.data(), sizeof(double) * M);
+    if (rho) memcpy(rho, o.rho.data(), sizeof(double) * o.P);
+    if (lam) memcpy(lam, o.lam.data(), sizeof(double) * o.P);
+    if (diag_inv) memcpy(diag_inv, o.diag_inv.data(), sizeof(double) * M);
+    return TDS_OK;
+}
+
+int tdsolve_prepare_host_general(const double* lower, const double* diag, const double* upper,
+                                 int64_t M, int32_t P, int64_t* starts, double* wR, double* wL,
+                                 double* rho, double* lam, double* diag_inv) {
+    HostTables o;
+    int rc = host_prepare_general(lower, diag, upper, M, P, o);
     if (rc) return rc;
     if (starts) memcpy(starts, o.starts.data(), sizeof(int64_t) * (o.P + 1));
     if (wR) memcpy(wR, o.wR.data(), sizeof(double) * M);

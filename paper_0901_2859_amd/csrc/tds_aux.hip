@@ -18,6 +18,7 @@ template <typename Fin, typename Xin>
 __global__ __launch_bounds__(kWG) void k_resid_part(const Fin* __restrict__ F,
                                                     const Xin* __restrict__ X, int64_t N,
                                                     int64_t M, const double* __restrict__ a64,
+                                                    const double* __restrict__ l64,
                                                     const double* __restrict__ b64,
                                                     double* __restrict__ part) {
     const int64_t n = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(kWG) void k_resid_part(const Fin* __restrict__ F,
     for (int64_t i = lo; i < hi; ++i) {
         const double x = (double)X[i * N + n];
         double r = (double)F[i * N + n] - b64[i] * x;
-        if (i > 0) r -= a64[i - 1] * (double)X[(i - 1) * N + n];
+        if (i > 0) r -= l64[i - 1] * (double)X[(i - 1) * N + n];
         if (i + 1 < M) r -= a64[i] * (double)X[(i + 1) * N + n];
         const double f = (double)F[i * N + n];
         rmx = fmax(rmx, fabs(r));
@@ -115,15 +116,15 @@ hipError_t launch_residual(const DevTables& t, const void* F, const void* X, int
     switch (mode) {
         case TDS_F64:
             hipLaunchKernelGGL((k_resid_part<double, double>), g, dim3(kWG), 0, s,
-                               (const double*)F, (const double*)X, N, t.M, t.a64, t.b64, part);
+                               (const double*)F, (const double*)X, N, t.M, t.a64, t.l64, t.b64, part);
             break;
         case TDS_F32:
             hipLaunchKernelGGL((k_resid_part<float, float>), g, dim3(kWG), 0, s,
-                               (const float*)F, (const float*)X, N, t.M, t.a64, t.b64, part);
+                               (const float*)F, (const float*)X, N, t.M, t.a64, t.l64, t.b64, part);
             break;
         default:
             hipLaunchKernelGGL((k_resid_part<float, double>), g, dim3(kWG), 0, s,
-                               (const float*)F, (const double*)X, N, t.M, t.a64, t.b64, part);
+                               (const float*)F, (const double*)X, N, t.M, t.a64, t.l64, t.b64, part);
             break;
     }
     hipError_t e = hipGetLastError();

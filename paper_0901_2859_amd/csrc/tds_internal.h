@@ -26,20 +26,24 @@ struct DevTables {
     int64_t M = 0;
     int32_t P = 0;
     int32_t max_rows = 0;      // largest t_j
+    int32_t general = 0;       // 1: non-symmetric A (sub-diagonal in l64/l32/inl*)
     int64_t* starts = nullptr;
     double* wR = nullptr;      // row of A^{-1} at the segment's right interface row
     double* wL = nullptr;      // row of A^{-1} at the segment's left interface row
     double* rho = nullptr;     // P: Z^R transfer factor from interface k to k+1
     double* lam = nullptr;     // P: Z^L transfer factor from interface k+1 to k
-    double* a64 = nullptr;     // a[i] (0 at i = M-1)
+    double* a64 = nullptr;     // super-diagonal A[i][i+1] (0 at i = M-1)
+    double* l64 = nullptr;     // sub-diagonal A[i+1][i] (= a64 for symmetric A)
     double* b64 = nullptr;     // b[i]
     double* cp64 = nullptr;    // block-restarted elimination: x_i + cp_i x_{i+1} = d_i
     double* rd64 = nullptr;    // 1 / pivot
-    // Block-interior coupling a[i] to row i+1, zero at every block's last
-    // interior row (so a block's zero-boundary system ends there); serves as
-    // the super-diagonal of row i and, read at i-1, the sub-diagonal of row i.
+    // Block-interior couplings, zero at every block's last interior row (so
+    // a block's zero-boundary system ends there): in = super-diagonal of row
+    // i (A[i][i+1]); inl = sub-diagonal, read at i-1 for row i (A[i][i-1]).
     double* in64 = nullptr;
     float* in32 = nullptr;
+    double* inl64 = nullptr;
+    float* inl32 = nullptr;
     // Block responses to the interface values: x = x0 + xl u + xr v, with
     // u = T^{-1}(-a_{i0-1} e_first), v = T^{-1}(-a_{i1} e_last) (Lemma 1).
     double* u = nullptr;
@@ -47,6 +51,7 @@ struct DevTables {
     const double2* wpad = nullptr;         // beta weights (wR, wL) per block,
     int32_t wpad_rows = 0;                 //   padded to wpad_rows with zeros
     float* a32 = nullptr;
+    float* l32 = nullptr;
     float* cp32 = nullptr;
     float* rd32 = nullptr;
 };
@@ -60,10 +65,14 @@ struct HostTables {
     double max_ratio = 0.0;
     std::vector<int64_t> starts;
     std::vector<double> wR, wL, rho, lam, diag_inv, a64, b64, cp64, rd64, u, v;
+    std::vector<double> l64;               // sub-diagonal (a copy of a64 if symmetric)
+    int32_t general = 0;                   // 1: non-symmetric A (by similarity)
 };
 
 int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
                  HostTables& out);
+int host_prepare_general(const double* lo, const double* diag, const double* up,
+                         int64_t M, int32_t P, HostTables& out);
 int32_t default_blocks(int64_t M);
 
 // Kernel launchers (tdsolve_kernels.hip).  All return hipError_t.

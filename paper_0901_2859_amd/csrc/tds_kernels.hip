@@ -285,15 +285,18 @@ __device__ __forceinline__ void sweep_load(const Fin* __restrict__ fb, int lane,
     for (int r = 0; r < TMAX; ++r) f[r] = (fb + (int64_t)(r < cnt ? r : cnt - 1) * N)[lane];
 }
 
-template <int TMAX, typename Fin, typename Xout, int KIND>
+template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
 __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restrict__ xb, int lane,
                                            int64_t N, int cnt, double cl, double xl, double cr,
                                            double xr, const DevTables& T, int64_t i0,
                                            float* __restrict__ my_f, int passes) {
-    const cptr<double> a64 = cst(T.a64 + i0), b64 = cst(T.b64 + i0);
+    // sub-diagonal: its own table for a non-symmetric A, else the one
+    // off-diagonal table (one scalar stream fewer per row)
+    const cptr<double> l64 = cst((GEN ? T.l64 : T.a64) + i0), b64 = cst(T.b64 + i0);
     const cptr<double> cp64 = cst(T.cp64 + i0), rd64 = cst(T.rd64 + i0);
     const cptr<double> uu = cst(T.u + i0), vv = cst(T.v + i0);
-    const cptr<float> a32 = cst(T.a32 + i0), cp32 = cst(T.cp32 + i0), rd32 = cst(T.rd32 + i0);
+    const cptr<float> l32 = cst((GEN ? T.l32 : T.a32) + i0), cp32 = cst(T.cp32 + i0),
+                      rd32 = cst(T.rd32 + i0);
 
     if constexpr (KIND == kSweep64 || KIND == kSweep32) {
         // one pass: the known boundary values are moved to the right-hand
@@ -310,7 +313,7 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
 #pragma unroll
             for (int r = 0; r < TMAX; ++r) {
                 const double prev = (r > 0) ? d[r - 1] : 0.0;
-                const double sub = (r > 0) ? a64[r - 1] : 0.0;
+                const double sub = (r > 0) ? l64[r - 1] : 0.0;
                 d[r] = (g(r) - sub * prev) * rd64[r];
             }
             double x = 0.0;
@@ -324,7 +327,7 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
 #pragma unroll
             for (int r = 0; r < TMAX; ++r) {
                 const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                const float sub = (r > 0) ? a32[r - 1] : 0.0f;
+                const float sub = (r > 0) ? l32[r - 1] : 0.0f;
                 w[r] = ((float)g(r) - sub * prev) * rd32[r];
             }
             float x = 0.0f;
@@ -343,14 +346,14 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
         // carry a row-dependent condition.)
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) my_f[r * kWG] = (float)f[r];
-        const cptr<float> in32 = cst(T.in32 + i0);
+        const cptr<float> inl32 = cst((GEN ? T.inl32 : T.in32) + i0);
         double x[TMAX];
         float w[TMAX];
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) {
             if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
             const float prev = (r > 0) ? w[r - 1] : 0.0f;
-            const float sub = (r > 0) ? in32[r - 1] : 0.0f;
+            const float sub = (r > 0) ? inl32[r - 1] : 0.0f;
             w[r] = (my_f[r * kWG] - sub * prev) * rd32[r];
         }
         {
@@ -370,8 +373,9 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
             int z;
             asm volatile("s_mov_b32 %0, 0" : "=s"(z));
             const cptr<double> in64p = cst(T.in64 + i0) + z;
+            const cptr<double> inl64p = GEN ? cst(T.inl64 + i0) + z : in64p;
             const cptr<double> b64p = b64 + z;
-            const cptr<float> in32p = in32 + z, cp32p = cp32 + z, rd32p = rd32 + z;
+            const cptr<float> inl32p = inl32 + z, cp32p = cp32 + z, rd32p = rd32 + z;
 #pragma unroll
             for (int r = 0; r < TMAX; ++r) {
                 // bound the scheduler's look-ahead: the residuals do not
@@ -379,10 +383,10 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
                 // ahead of it would hold 64 FP64 values in registers
                 if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
                 double res = (double)my_f[r * kWG] - b64p[r] * x[r];
-                if (r > 0) res -= in64p[r - 1] * x[r - 1];
+                if (r > 0) res -= inl64p[r - 1] * x[r - 1];
                 if (r + 1 < TMAX) res -= in64p[r] * x[r + 1];
                 const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                const float sub = (r > 0) ? in32p[r - 1] : 0.0f;
+                const float sub = (r > 0) ? inl32p[r - 1] : 0.0f;
                 w[r] = ((float)res - sub * prev) * rd32p[r];
             }
             float dl = 0.0f;
@@ -399,7 +403,7 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
     }
 }
 
-template <int TMAX, typename Fin, typename Xout, int KIND>
+template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
 __device__ __forceinline__ void sweep_item(const DevTables& T, const Fin* __restrict__ F,
                                            Xout* __restrict__ X, int64_t N, int32_t j,
                                            int64_t tile, const double* __restrict__ xsep,
@@ -412,25 +416,26 @@ __device__ __forceinline__ void sweep_item(const DevTables& T, const Fin* __rest
     if (n >= N) return;
     const double xl = (j > 0) ? xsep[(int64_t)(j - 1) * N + n] : 0.0;
     const double xr = (j < P - 1) ? xsep[(int64_t)j * N + n] : 0.0;
-    const double cl = (j > 0) ? cst(T.a64)[i0 - 1] : 0.0;         // A[i0][i0-1]
+    const double cl = (j > 0) ? cst(GEN ? T.l64 : T.a64)[i0 - 1] : 0.0;   // A[i0][i0-1]
     const double cr = (j < P - 1) ? cst(T.a64)[seg_hi - 1] : 0.0; // A[i1][i1+1]
     if (j > 0) X[seg_lo * N + n] = (Xout)xl;
     Fin f[TMAX];
     const int lane = threadIdx.x;
     sweep_load<TMAX, Fin>(F + i0 * N + tile * kWG, lane, N, cnt, f);
-    sweep_body<TMAX, Fin, Xout, KIND>(f, X + i0 * N + tile * kWG, lane, N, cnt, cl, xl, cr, xr, T,
+    sweep_body<TMAX, Fin, Xout, KIND, GEN>(f, X + i0 * N + tile * kWG, lane, N, cnt, cl, xl, cr, xr, T,
                                       i0, s_f + lane, passes);
 }
 
 // Block sweep for blocks longer than the register path holds: the forward
 // elimination is kept in X itself and read back by the back substitution.
 // FP64 arithmetic except for KIND == kSweep32.
-template <typename Fin, typename Xout, int KIND>
+template <typename Fin, typename Xout, int KIND, bool GEN>
 __device__ __forceinline__ void sweep_stream_item(const DevTables& T, const Fin* __restrict__ F,
                                                   Xout* __restrict__ X, int64_t N, int32_t j,
                                                   int64_t tile, const double* __restrict__ xsep) {
     const int32_t P = T.P;
-    const cptr<double> a64 = cst(T.a64), cp64 = cst(T.cp64), rd64 = cst(T.rd64);
+    const cptr<double> a64 = cst(T.a64), l64 = cst(GEN ? T.l64 : T.a64), cp64 = cst(T.cp64),
+                       rd64 = cst(T.rd64);
     const int64_t seg_lo = cst(T.starts)[j], seg_hi = cst(T.starts)[j + 1];
     const int64_t i0 = (j == 0) ? seg_lo : seg_lo + 1;
     const int64_t cnt = seg_hi - i0;
@@ -438,7 +443,7 @@ __device__ __forceinline__ void sweep_stream_item(const DevTables& T, const Fin*
     if (n >= N) return;
     const double xl = (j > 0) ? xsep[(int64_t)(j - 1) * N + n] : 0.0;
     const double xr = (j < P - 1) ? xsep[(int64_t)j * N + n] : 0.0;
-    const double cl = (j > 0) ? a64[i0 - 1] : 0.0;
+    const double cl = (j > 0) ? l64[i0 - 1] : 0.0;
     const double cr = (j < P - 1) ? a64[seg_hi - 1] : 0.0;
     if (j > 0) X[seg_lo * N + n] = (Xout)xl;
     double prev = 0.0;
@@ -447,7 +452,7 @@ __device__ __forceinline__ void sweep_stream_item(const DevTables& T, const Fin*
         double v = (double)F[i * N + n];
         if (r == 0) v -= cl * xl;
         if (r == cnt - 1) v -= cr * xr;
-        const double sub = (r > 0) ? a64[i - 1] : 0.0;
+        const double sub = (r > 0) ? l64[i - 1] : 0.0;
         double d;
         if (KIND == kSweep32)
             d = (double)(((float)v - (float)sub * (float)prev) * (float)rd64[i]);
@@ -493,7 +498,7 @@ __global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface(
     iface_item(T, N, per, G, betaR, betaL, xsep, (int64_t)blockIdx.x, S);
 }
 
-template <int TMAX, typename Fin, typename Xout, int KIND>
+template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
 __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_reg(
     DevTables T, const Fin* __restrict__ F, Xout* __restrict__ X, int64_t N,
     const double* __restrict__ xsep, int passes) {
@@ -501,15 +506,15 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     // lanes per block row, conflict-free) so that its VGPRs hold only x and
     // the FP32 elimination values
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
-    sweep_item<TMAX, Fin, Xout, KIND>(T, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, xsep,
+    sweep_item<TMAX, Fin, Xout, KIND, GEN>(T, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, xsep,
                                       passes, s_f);
 }
 
-template <typename Fin, typename Xout, int KIND>
+template <typename Fin, typename Xout, int KIND, bool GEN>
 __global__ __launch_bounds__(kWG) void k_sweep_stream(DevTables T, const Fin* __restrict__ F,
                                                       Xout* __restrict__ X, int64_t N,
                                                       const double* __restrict__ xsep) {
-    sweep_stream_item<Fin, Xout, KIND>(T, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x,
+    sweep_stream_item<Fin, Xout, KIND, GEN>(T, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x,
                                        xsep);
 }
 
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
     if (local >= (int64_t)d.T.P * tiles) return;
-    sweep_item<TMAX, Fin, Xout, KIND>(d.T, (const Fin*)d.F, (Xout*)d.X, d.N,
+    sweep_item<TMAX, Fin, Xout, KIND, false>(d.T, (const Fin*)d.F, (Xout*)d.X, d.N,
                                       (int32_t)(local / tiles), local % tiles, d.xsep, passes,
                                       s_f);
 }
@@ -626,13 +631,13 @@ hipError_t launch_iface(const DevTables& t, const double* betaR, const double* b
     return hipGetLastError();
 }
 
-template <typename Fin, typename Xout, int KIND>
-static void go_sweep(const DevTables& t, const void* F, void* X, int64_t N, int passes,
-                     const double* xsep, hipStream_t s) {
+template <typename Fin, typename Xout, int KIND, bool GEN>
+static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, int passes,
+                       const double* xsep, hipStream_t s) {
     const int m = t.max_rows;
     const dim3 g = grid2(N, t.P);
 #define TDS_SWEEP(TM)                                                                        \
-    hipLaunchKernelGGL((k_sweep_reg<TM, Fin, Xout, KIND>), g, dim3(kWG), 0, s, t,            \
+    hipLaunchKernelGGL((k_sweep_reg<TM, Fin, Xout, KIND, GEN>), g, dim3(kWG), 0, s, t,       \
                        (const Fin*)F, (Xout*)X, N, xsep, passes)
     if (m <= 16)
         TDS_SWEEP(16);
@@ -643,9 +648,19 @@ static void go_sweep(const DevTables& t, const void* F, void* X, int64_t N, int 
     else if (m <= kRegMaxRows && KIND != kSweepRefined)
         TDS_SWEEP(128);
     else
-        hipLaunchKernelGGL((k_sweep_stream<Fin, Xout, KIND == kSweep32 ? kSweep32 : kSweep64>),
-                           g, dim3(kWG), 0, s, t, (const Fin*)F, (Xout*)X, N, xsep);
+        hipLaunchKernelGGL(
+            (k_sweep_stream<Fin, Xout, KIND == kSweep32 ? kSweep32 : kSweep64, GEN>), g,
+            dim3(kWG), 0, s, t, (const Fin*)F, (Xout*)X, N, xsep);
 #undef TDS_SWEEP
+}
+
+template <typename Fin, typename Xout, int KIND>
+static void go_sweep(const DevTables& t, const void* F, void* X, int64_t N, int passes,
+                     const double* xsep, hipStream_t s) {
+    if (t.general)
+        go_sweep_t<Fin, Xout, KIND, true>(t, F, X, N, passes, xsep, s);
+    else
+        go_sweep_t<Fin, Xout, KIND, false>(t, F, X, N, passes, xsep, s);
 }
 
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, int mode,

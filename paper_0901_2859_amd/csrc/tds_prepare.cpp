@@ -44,6 +44,48 @@ int32_t default_blocks(int64_t M) {
     return (int32_t)std::min<int64_t>(P, 1 << 20);
 }
 
+// Block-restarted elimination of every block's interior rows and the
+// block's responses u, v to its left / right interface value (Lemma 1), for
+// the matrix with sub-diagonal lo (A[i+1][i] = lo[i]), diagonal o.b64 and
+// super-diagonal up (A[i][i+1] = up[i]).
+static int block_tables(HostTables& o, const double* lo, const double* up) {
+    const int64_t M = o.M;
+    const int32_t P = o.P;
+    const double* b = o.b64.data();
+    const auto& s = o.starts;
+    o.cp64.assign(M, 0.0);
+    o.rd64.assign(M, 0.0);
+    o.u.assign(M, 0.0);
+    o.v.assign(M, 0.0);
+    for (int32_t j = 0; j < P; ++j) {
+        const int64_t i0 = (j == 0) ? s[0] : s[j] + 1;
+        const int64_t i1 = s[j + 1] - 1;
+        double cprev = 0.0;
+        for (int64_t i = i0; i <= i1; ++i) {
+            double den = b[i] - (i > i0 ? lo[i - 1] * cprev : 0.0);
+            if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
+            o.rd64[i] = 1.0 / den;
+            o.cp64[i] = (i < i1) ? up[i] / den : 0.0;
+            cprev = o.cp64[i];
+        }
+        const double cl = (j > 0) ? lo[i0 - 1] : 0.0;     // A[i0][i0-1]
+        const double cr = (j < P - 1) ? up[i1] : 0.0;     // A[i1][i1+1]
+        // u = T^{-1}(-cl e_first): forward elimination then back substitution
+        double d = -cl * o.rd64[i0];
+        o.u[i0] = d;
+        for (int64_t i = i0 + 1; i <= i1; ++i) {
+            d = (0.0 - lo[i - 1] * d) * o.rd64[i];
+            o.u[i] = d;
+        }
+        for (int64_t i = i1 - 1; i >= i0; --i) o.u[i] -= o.cp64[i] * o.u[i + 1];
+        // v = T^{-1}(-cr e_last): only the last row is non-zero after the
+        // forward elimination
+        o.v[i1] = -cr * o.rd64[i1];
+        for (int64_t i = i1 - 1; i >= i0; --i) o.v[i] = -o.cp64[i] * o.v[i + 1];
+    }
+    return TDS_OK;
+}
+
 int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
                  HostTables& o) {
     if (M < 1 || b == nullptr || (M > 1 && a == nullptr)) return TDS_EINVAL;
@@ -157,39 +199,69 @@ int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
         o.lam[k] = pl;
     }
 
-    // block-restarted elimination of every block's interior rows, and the
-    // block's responses u, v to its left / right interface value
-    o.cp64.assign(M, 0.0);
-    o.rd64.assign(M, 0.0);
-    o.u.assign(M, 0.0);
-    o.v.assign(M, 0.0);
-    for (int32_t j = 0; j < P; ++j) {
-        const int64_t i0 = (j == 0) ? s[0] : s[j] + 1;
-        const int64_t i1 = s[j + 1] - 1;
-        double cprev = 0.0;
-        for (int64_t i = i0; i <= i1; ++i) {
-            double den = b[i] - (i > i0 ? A[i - 1] * cprev : 0.0);
-            if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
-            o.rd64[i] = 1.0 / den;
-            o.cp64[i] = (i < i1) ? A[i] / den : 0.0;
-            cprev = o.cp64[i];
-        }
-        const double cl = (j > 0) ? A[i0 - 1] : 0.0;      // A[i0][i0-1]
-        const double cr = (j < P - 1) ? A[i1] : 0.0;      // A[i1][i1+1]
-        // u = T^{-1}(-cl e_first): forward elimination then back substitution
-        double d = -cl * o.rd64[i0];
-        o.u[i0] = d;
-        for (int64_t i = i0 + 1; i <= i1; ++i) {
-            d = (0.0 - A[i - 1] * d) * o.rd64[i];
-            o.u[i] = d;
-        }
-        for (int64_t i = i1 - 1; i >= i0; --i) o.u[i] -= o.cp64[i] * o.u[i + 1];
-        // v = T^{-1}(-cr e_last): only the last row is non-zero after the
-        // forward elimination
-        o.v[i1] = -cr * o.rd64[i1];
-        for (int64_t i = i1 - 1; i >= i0; --i) o.v[i] = -o.cp64[i] * o.v[i + 1];
+    o.l64 = o.a64;
+    o.general = 0;
+    return block_tables(o, A, A);
+}
+
+// Non-symmetric tridiagonal A (section "Nonsymmetrical matrices"): when
+// lo[i] * up[i] > 0 for every i, the diagonal similarity S = D^{-1} A D with
+// d_{i+1} / d_i = q_i = sqrt(lo[i] / up[i]) is symmetric, with off-diagonal
+// sigma_i = sign(up[i]) sqrt(lo[i] up[i]).  The preliminary step runs on S;
+// since A^{-1} = D S^{-1} D^{-1}, the rows of A^{-1} at the interface rows
+// and the transfer factors follow by the ratios d_k / d_i, which are
+// products of the q_m between the two rows (never the absolute d_i, which
+// can overflow on long systems).  The block sweeps run on A itself.
+int host_prepare_general(const double* lo, const double* diag, const double* up, int64_t M,
+                         int32_t P, HostTables& o) {
+    if (M < 1 || diag == nullptr || (M > 1 && (lo == nullptr || up == nullptr)))
+        return TDS_EINVAL;
+    std::vector<double> sig(M > 1 ? M - 1 : 1, 0.0), q(M > 1 ? M - 1 : 1, 1.0);
+    for (int64_t i = 0; i + 1 < M; ++i) {
+        if (bad(lo[i]) || bad(up[i])) return TDS_EINVAL;
+        if (!((lo[i] > 0.0 && up[i] > 0.0) || (lo[i] < 0.0 && up[i] < 0.0)))
+            return TDS_EUNSUPPORTED;
+        const double sl = sqrt(fabs(lo[i])), su = sqrt(fabs(up[i]));
+        sig[i] = (up[i] > 0.0 ? 1.0 : -1.0) * sl * su;
+        q[i] = sl / su;
     }
-    return TDS_OK;
+    int rc = host_prepare(sig.data(), diag, M, P, o);
+    if (rc) return rc;
+    P = o.P;
+    const auto& s = o.starts;
+    // weights: wR on segment j is row s_{j+1} of A^{-1}, wL row s_j
+    for (int32_t j = 0; j < P; ++j) {
+        if (j < P - 1) {
+            double r = 1.0;                      // d_{s_{j+1}} / d_i
+            for (int64_t i = s[j + 1] - 1; i >= s[j]; --i) {
+                r *= q[i];
+                o.wR[i] *= r;
+            }
+        }
+        if (j > 0) {
+            double r = 1.0;                      // d_{s_j} / d_i
+            for (int64_t i = s[j]; i < s[j + 1]; ++i) {
+                o.wL[i] *= r;
+                if (i + 1 < M) r /= q[i];
+            }
+        }
+    }
+    // transfer factors between interface rows s_k and s_{k+1}
+    for (int32_t k = 1; k + 1 <= P - 1; ++k) {
+        double r = 1.0;                          // d_{s_{k+1}} / d_{s_k}
+        for (int64_t m = s[k]; m < s[k + 1]; ++m) r *= q[m];
+        o.rho[k] *= r;
+        o.lam[k] /= r;
+    }
+    // sweep tables of A itself
+    o.a64.assign(M, 0.0);
+    o.l64.assign(M, 0.0);
+    for (int64_t i = 0; i + 1 < M; ++i) {
+        o.a64[i] = up[i];
+        o.l64[i] = lo[i];
+    }
+    o.general = 1;
+    return block_tables(o, o.l64.data(), o.a64.data());
 }
 
 }  // namespace tds

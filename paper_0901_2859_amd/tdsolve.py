@@ -26,11 +26,13 @@ _F_DTYPE = {0: "float64", 1: "float32", 2: "float32", 3: "float32"}
 _X_DTYPE = {0: "float64", 1: "float64", 2: "float32", 3: "float64"}
 
 SYMBOLS = [
-    "tdsolve_prepare", "tdsolve_series", "tdsolve_components", "tdsolve_backward",
+    "tdsolve_prepare", "tdsolve_prepare_general", "tdsolve_series", "tdsolve_components",
+    "tdsolve_backward",
     "tdsolve_residual", "tdsolve_set_refinement", "tdsolve_info", "tdsolve_prepare_host",
     "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
+    "tdsolve_prepare_host_general",
 ]
 
 _lib = None
@@ -46,7 +48,7 @@ class TdsError(RuntimeError):
 class Info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("P", ctypes.c_int32), ("max_block", ctypes.c_int32),
                 ("dominant", ctypes.c_int32), ("refine_passes", ctypes.c_int32),
-                ("max_ratio", ctypes.c_double)]
+                ("max_ratio", ctypes.c_double), ("general", ctypes.c_int32)]
 
 
 def lib():
@@ -60,6 +62,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
     L.tdsolve_prepare.argtypes = [dp, dp, i64, i32, ctypes.POINTER(vp)]
+    L.tdsolve_prepare_general.argtypes = [dp, dp, dp, i64, i32, ctypes.POINTER(vp)]
     L.tdsolve_series.argtypes = [vp, vp, vp, i64, i32, vp]
     L.tdsolve_components.argtypes = [vp, vp, vp, i64, i32, vp]
     L.tdsolve_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp]
@@ -67,6 +70,7 @@ def lib():
     L.tdsolve_set_refinement.argtypes = [vp, i32]
     L.tdsolve_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.tdsolve_prepare_host.argtypes = [dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
+    L.tdsolve_prepare_host_general.argtypes = [dp, dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
     L.tdsolve_default_blocks.argtypes = [i64]
     L.tdsolve_default_blocks.restype = i32
     L.tdsolve_destroy.argtypes = [vp]
@@ -126,6 +130,24 @@ def prepare_host(a, b, P: int):
     return dict(starts=starts, wR=wR, wL=wL, rho=rho, lam=lam, diag_inv=dinv, P=P, M=M)
 
 
+def prepare_host_general(lower, diag, upper, P: int):
+    """prepare_host() for a non-symmetric A (tdsolve_prepare_host_general)."""
+    L = lib()
+    d = _host_f64(diag)
+    M = d.shape[0]
+    lo = _host_f64(lower) if M > 1 else np.zeros(1)
+    up = _host_f64(upper) if M > 1 else np.zeros(1)
+    if P == 0:
+        P = default_blocks(M)
+    starts = np.zeros(P + 1, dtype=np.int64)
+    wR, wL, dinv = np.zeros(M), np.zeros(M), np.zeros(M)
+    rho, lam = np.zeros(P), np.zeros(P)
+    _check(L.tdsolve_prepare_host_general(_ptr(lo), _ptr(d), _ptr(up), M, P, _ptr(starts),
+                                          _ptr(wR), _ptr(wL), _ptr(rho), _ptr(lam), _ptr(dinv)),
+           "tdsolve_prepare_host_general")
+    return dict(starts=starts, wR=wR, wL=wL, rho=rho, lam=lam, diag_inv=dinv, P=P, M=M)
+
+
 def _stream_ptr(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -147,6 +169,27 @@ class Plan:
         self.M = M
         info = self.info()
         self.P = info.P
+
+    @classmethod
+    def general(cls, lower, diag, upper, P: Optional[int] = None):
+        """Plan for a non-symmetric tridiagonal matrix (row i: lower[i-1]
+        x_{i-1} + diag[i] x_i + upper[i] x_{i+1}); needs lower[i] * upper[i]
+        > 0 (tdsolve_prepare_general).  No backward()."""
+        L = lib()
+        d = _host_f64(diag)
+        M = int(d.shape[0])
+        lo = _host_f64(lower) if M > 1 else np.zeros(1)
+        up = _host_f64(upper) if M > 1 else np.zeros(1)
+        if M > 1 and (lo.shape[0] != M - 1 or up.shape[0] != M - 1):
+            raise ValueError("lower and upper need M-1 entries")
+        h = ctypes.c_void_p()
+        _check(L.tdsolve_prepare_general(_ptr(lo), _ptr(d), _ptr(up), M, int(P or 0),
+                                         ctypes.byref(h)), "tdsolve_prepare_general")
+        self = cls.__new__(cls)
+        self._h = h
+        self.M = M
+        self.P = self.info().P
+        return self
 
     def info(self) -> Info:
         out = Info()

@@ -1,0 +1,97 @@
+"""GPU parity for non-symmetric tridiagonal matrices (tdsolve_prepare_general:
+the diagonal similarity to a symmetric matrix in the preliminary step, the
+block sweeps on A itself) against the CPU oracle's general elimination.
+
+Tolerance as for the symmetric parity tests, with the rows of the
+non-symmetric A^{-1} at the interface rows in the conditioning factor:
+e_n <= 1e-11 + 8 (t + 2P) u cond_n, cond_n = max_k sum_i |A^{-1}(s_k, i)|
+|F_i,n| / |X_or,n|_inf.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import method  # noqa: E402
+from paper_0901_2859_amd import tdsolve as t  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _rand_general(rng, M, gamma=None):
+    if gamma is not None:
+        # convection-diffusion, central differences: lower = -1 - g, upper = -1 + g
+        lo = np.full(M - 1, -1.0 - gamma)
+        up = np.full(M - 1, -1.0 + gamma)
+        d = np.full(M, 2.0 + 0.05)
+        return lo, d, up
+    up = rng.uniform(0.2, 1.0, size=M - 1) * rng.choice([-1.0, 1.0], size=M - 1)
+    lo = np.sign(up) * rng.uniform(0.2, 1.0, size=M - 1)
+    d = (np.concatenate([[0], np.abs(lo)]) + np.concatenate([np.abs(up), [0]]) + 0.3
+         + rng.uniform(0, 0.5, size=M)) * rng.choice([-1.0, 1.0], size=M)
+    return lo, d, up
+
+
+def _oracle(lo, d, up, F):
+    low = np.concatenate([[0.0], lo])
+    upp = np.concatenate([up, [0.0]])
+    return np.stack([oracle.tridiag_general(low, d, upp, F[:, n]) for n in range(F.shape[1])], 1)
+
+
+def _tol(lo, d, up, F, ref, P):
+    M = len(d)
+    if P < 2:
+        return np.full(F.shape[1], 1e-11)
+    tt, s = method.partition(M, P)
+    Ainv = np.linalg.inv(np.diag(d) + np.diag(lo, -1) + np.diag(up, 1))
+    G = Ainv[s[1:P], :]
+    cond = (np.abs(G) @ np.abs(F)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
+    return 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+
+
+def _check(X, ref, tol, what):
+    e = np.max(np.abs(np.asarray(X, np.float64) - ref), axis=0) / np.maximum(
+        np.max(np.abs(ref), axis=0), 1e-300)
+    bad = np.nonzero(e > tol)[0]
+    assert bad.size == 0, f"{what}: columns {bad[:5]} e={e[bad[:5]]} tol={tol[bad[:5]]}"
+
+
+@pytest.mark.parametrize("M,N,P,gamma", [
+    (64, 16, 4, None), (300, 300, 10, None), (1000, 257, 16, None), (1000, 100, 13, None),
+    (2000, 70, 2, None), (4096, 200, 64, 0.5), (1500, 90, 20, -0.8), (2, 3, 1, None),
+])
+def test_general_parity_all_modes(M, N, P, gamma):
+    print(f"general M={M} N={N} P={P} gamma={gamma}", flush=True)
+    rng = np.random.default_rng(M + N + P)
+    lo, d, up = _rand_general(rng, M, gamma)
+    F32 = rng.uniform(-1, 1, size=(M, N)).astype(np.float32)
+    Fw = F32.astype(np.float64)
+    ref = _oracle(lo, d, up, Fw)
+    plan = t.Plan.general(lo, d, up, P)
+    assert plan.info().general == 1
+    tol = _tol(lo, d, up, Fw, ref, P)
+    Fd, Fs = torch.from_numpy(Fw).to(DEV), torch.from_numpy(F32).to(DEV)
+    for mode, Fin in (("f64", Fd), ("f32_refined", Fs), ("f32_wide", Fs)):
+        _check(plan.solve(Fin, mode=mode).cpu().numpy(), ref, tol, mode)
+    X32 = plan.solve(Fs, mode="f32").cpu().numpy()
+    assert np.max(np.abs(X32 - ref)) <= 2e-4 * np.max(np.abs(ref))
+    # residual kernel with the non-symmetric couplings, on a solution
+    # perturbed well above rounding so that a swapped coupling would show
+    Xh = ref + 1e-6 * rng.uniform(-1, 1, size=ref.shape)
+    eta, r2 = plan.residual(Fd, torch.from_numpy(Xh).to(DEV), mode="f64")
+    R = Fw - d[:, None] * Xh
+    R[1:] -= lo[:, None] * Xh[:-1]
+    R[:-1] -= up[:, None] * Xh[1:]
+    r2_np = np.linalg.norm(R, axis=0) / np.linalg.norm(Fw, axis=0)
+    assert np.allclose(r2.cpu().numpy(), r2_np, rtol=1e-8)
+
+
+def test_general_backward_is_unsupported():
+    rng = np.random.default_rng(1)
+    lo, d, up = _rand_general(rng, 100)
+    plan = t.Plan.general(lo, d, up, 4)
+    X = torch.zeros((100, 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(t.TdsError):
+        plan.backward(X, X, mode="f64")

@@ -153,3 +153,72 @@ def test_dominance_ratios_bounded():
     # ratios are the Z transfer factors; |rho|, |lam| <= 1 under dominance (Theorem 4)
     h = t.prepare_host(a, b, 10)
     assert np.all(np.abs(h["rho"]) <= 1.0) and np.all(np.abs(h["lam"]) <= 1.0)
+
+
+def _rand_general(rng, M):
+    """Non-symmetric, diagonally dominant, lower[i] * upper[i] > 0."""
+    up = rng.uniform(0.2, 1.0, size=M - 1) * rng.choice([-1.0, 1.0], size=M - 1)
+    lo = np.sign(up) * rng.uniform(0.2, 1.0, size=M - 1)
+    d = (np.concatenate([[0], np.abs(lo)]) + np.concatenate([np.abs(up), [0]]) + 0.3
+         + rng.uniform(0, 0.5, size=M)) * rng.choice([-1.0, 1.0], size=M)
+    return lo, d, up
+
+
+def _dense(lo, d, up):
+    return np.diag(d) + np.diag(lo, -1) + np.diag(up, 1)
+
+
+@pytest.mark.parametrize("M,P", [(64, 4), (67, 5), (200, 16), (9, 4)])
+def test_prepare_host_general_rows_of_inverse(M, P):
+    # weights = rows of A^{-1} at the interface rows (the non-symmetric A,
+    # not its symmetrisation), diagonal of A^{-1}
+    rng = np.random.default_rng(M * 11 + P)
+    lo, d, up = _rand_general(rng, M)
+    h = t.prepare_host_general(lo, d, up, P)
+    Ainv = np.linalg.inv(_dense(lo, d, up))
+    s = h["starts"]
+    for j in range(P):
+        a_, b_ = s[j], s[j + 1]
+        if j <= P - 2:
+            assert np.allclose(h["wR"][a_:b_], Ainv[s[j + 1], a_:b_], rtol=1e-12, atol=1e-15)
+        if j >= 1:
+            assert np.allclose(h["wL"][a_:b_], Ainv[s[j], a_:b_], rtol=1e-12, atol=1e-15)
+    assert np.allclose(h["diag_inv"], np.diag(Ainv), rtol=1e-12)
+
+
+@pytest.mark.parametrize("M,P", [(64, 4), (101, 7), (256, 32)])
+def test_replay_with_general_tables_matches_oracle(M, P):
+    # the per-RHS recurrences with the general tables give A^{-1} F at the
+    # interface rows, against the oracle's general elimination per column
+    rng = np.random.default_rng(M + 5 * P)
+    lo, d, up = _rand_general(rng, M)
+    F = rng.uniform(-1, 1, size=(M, 4))
+    h = t.prepare_host_general(lo, d, up, P)
+    xs = _replay(h, None, None, F)
+    low = np.concatenate([[0.0], lo])
+    upp = np.concatenate([up, [0.0]])
+    X = np.stack([oracle.tridiag_general(low, d, upp, F[:, n]) for n in range(F.shape[1])], 1)
+    assert np.max(np.abs(xs - X[h["starts"][1:P]])) <= 1e-12 * np.max(np.abs(X))
+
+
+def test_prepare_general_symmetric_input_matches_symmetric_tables():
+    rng = np.random.default_rng(3)
+    a, b = _rand(rng, 120)
+    hg = t.prepare_host_general(a, b, a, 8)
+    hs = t.prepare_host(a, b, 8)
+    for key in ("wR", "wL", "rho", "lam", "diag_inv"):
+        assert np.allclose(hg[key], hs[key], rtol=1e-14, atol=1e-300), key
+
+
+def test_prepare_general_errors_without_gpu():
+    L = t.lib()
+    h = ctypes.c_void_p()
+    lo, d, up = np.ones(9), np.full(10, 4.0), np.ones(9)
+    P_ = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    bad = up.copy(); bad[4] = -1.0                   # lower * upper < 0: no similarity
+    assert L.tdsolve_prepare_general(P_(lo), P_(d), P_(bad), 10, 2, ctypes.byref(h)) == -6
+    zero = lo.copy(); zero[2] = 0.0
+    assert L.tdsolve_prepare_general(P_(zero), P_(d), P_(up), 10, 2, ctypes.byref(h)) == -6
+    nan = lo.copy(); nan[0] = np.nan
+    assert L.tdsolve_prepare_general(P_(nan), P_(d), P_(up), 10, 2, ctypes.byref(h)) == -1
+    assert L.tdsolve_prepare_general(None, P_(d), P_(up), 10, 2, ctypes.byref(h)) == -1

@@ -271,3 +271,33 @@ def test_planted_mistake_in_sweep_is_caught():
     Xd = np.linalg.solve(method.dense(a, b), F)
     assert np.max(np.abs(oracle.thomas(-a, b, F) - Xd)) > 1e-6
     assert np.max(np.abs(oracle.thomas(np.roll(a, 1), b, F) - Xd)) > 1e-6
+
+
+# ---------------------------------------------------- general (non-symmetric)
+@pytest.mark.parametrize("M", [1, 2, 7, 60])
+def test_tridiag_general_matches_dense_lu(M):
+    # the oracle's plain elimination for a non-symmetric tridiagonal system
+    # against dense LU (numpy), on a diagonally dominant random matrix
+    rng = np.random.default_rng(40 + M)
+    lower = np.concatenate([[0.0], rng.uniform(-1, 1, size=M - 1)])
+    upper = np.concatenate([rng.uniform(-1, 1, size=M - 1), [0.0]])
+    diag = np.abs(lower) + np.abs(upper) + rng.uniform(0.5, 1.5, size=M)
+    A = np.diag(diag)
+    if M > 1:
+        A += np.diag(lower[1:], -1) + np.diag(upper[:-1], 1)
+    f = rng.uniform(-1, 1, size=M)
+    x = oracle.tridiag_general(lower, diag, upper, f)
+    assert np.allclose(x, np.linalg.solve(A, f), rtol=1e-13, atol=1e-14)
+
+
+def test_tridiag_general_manufactured_integer_solution():
+    # exact arithmetic: integer solution, small integer coefficients
+    M = 9
+    lower = np.array([0, 1, 2, 1, 3, 1, 2, 1, 1], dtype=float)
+    upper = np.array([2, 1, 1, 2, 1, 1, 3, 1, 0], dtype=float)
+    diag = np.full(M, 8.0)
+    x_true = np.arange(1, M + 1, dtype=float) * np.array([1, -1] * 4 + [1])
+    f = diag * x_true
+    f[1:] += lower[1:] * x_true[:-1]
+    f[:-1] += upper[:-1] * x_true[1:]
+    assert np.allclose(oracle.tridiag_general(lower, diag, upper, f), x_true, rtol=0, atol=1e-12)
