@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
+    p.add_argument("--interface", default="recurrence", choices=["recurrence", "dichotomy"],
+                   help="evaluation order of the interface values (single-matrix workloads)")
     p.add_argument("--graph", action="store_true",
                    help="time replays of a captured HIP graph per step instead of eager launches")
     p.add_argument("--sets", type=int, default=0,
@@ -134,8 +136,10 @@ class Single:
         self.plan = t.Plan(self.a, self.b, P)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
+        self.plan.set_interface(args.interface)
         self.unknowns = M * N
-        self.config = {"workload": self.name, "M": M, "N": N, "P": P}
+        self.config = {"workload": self.name, "M": M, "N": N, "P": P,
+                       "interface": args.interface}
 
     def sweep_bytes(self, mode):
         # the block sweep reads F, writes X, reads two interface values per

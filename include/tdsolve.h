@@ -158,6 +158,19 @@ int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N,
 int tdsolve_timing_enable(tds_handle h, int32_t on);
 int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
 
+/* Evaluation order of the interface values (Algorithm 3 step 2.2) for
+ * tdsolve_series and tdsolve_components of a single-matrix plan:
+ *   TDS_IFACE_RECURRENCE (default): Theorem 2's sums as two first-order
+ *     recurrences over the interface rows, O(P) per right-hand side;
+ *   TDS_IFACE_DICHOTOMY: Algorithm 4 (Theorem 3, eq. omega_i): the
+ *     interface rows level by level, each from its nearest known
+ *     neighbours, rows of one level in parallel; O(P log P) per
+ *     right-hand side and a work area of 2 (P + 1) N doubles more.
+ * Both give the same values up to rounding.  TDS_EINVAL for other values or
+ * a batch handle. */
+enum { TDS_IFACE_RECURRENCE = 0, TDS_IFACE_DICHOTOMY = 1 };
+int tdsolve_set_interface(tds_handle h, int32_t order);
+
 /* Number of refinement passes for TDS_F32_REFINED (0..8; default 2). */
 int tdsolve_set_refinement(tds_handle h, int32_t passes);
 

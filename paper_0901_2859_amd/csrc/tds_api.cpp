@@ -19,6 +19,7 @@ struct tds_plan {
     void* dev_mem = nullptr;
     double normA = 0.0;          // ||A||_inf
     int32_t passes = 2;          // refinement passes of TDS_F32_REFINED
+    int32_t iface = TDS_IFACE_RECURRENCE;   // interface-step evaluation order
     int device = 0;
     void* work = nullptr;        // grows with N
     size_t work_bytes = 0;
@@ -209,14 +210,39 @@ int check_common(tds_plan* h, int64_t N, int32_t mode) {
     return TDS_OK;
 }
 
-// beta + interface step into xsep
-int interface_step(tds_plan* h, const void* F, int64_t N, int32_t mode, double* xsep,
-                   double* betaR, double* betaL, hipStream_t s) {
-    const DevTables& t = h->dev;
-    if (t.P < 2) return TDS_OK;
-    if (launch_beta(t, F, mode != TDS_F64, N, betaR, betaL, s) != hipSuccess) return TDS_EHIP;
-    if (launch_iface(t, betaR, betaL, xsep, N, s) != hipSuccess) return TDS_EHIP;
+// Slices of the plan's work buffer for N right-hand sides: beta^R, beta^L
+// (P x N), the interface values (P-1 x N) and, for the dichotomy, its two
+// partial sums ((P+1) x N each).
+struct Work {
+    double* betaR;
+    double* betaL;
+    double* xsep;
+    double* SR;
+    double* SL;
+};
+
+int take_work(tds_plan* h, int64_t N, Work& w) {
+    const size_t P = (size_t)h->dev.P;
+    const size_t nb = align256(sizeof(double) * P * (size_t)N);
+    const size_t nx = align256(sizeof(double) * (P > 1 ? P - 1 : 1) * (size_t)N);
+    const size_t ns = (h->iface == TDS_IFACE_DICHOTOMY)
+                          ? align256(sizeof(double) * (P + 1) * (size_t)N) : 0;
+    const int rc = ensure_work(h, 2 * nb + nx + 2 * ns);
+    if (rc) return rc;
+    char* base = general_of(h);
+    w.betaR = (double*)base;
+    w.betaL = (double*)(base + nb);
+    w.xsep = (double*)(base + 2 * nb);
+    w.SR = ns ? (double*)(base + 2 * nb + nx) : nullptr;
+    w.SL = ns ? (double*)(base + 2 * nb + nx + ns) : nullptr;
     return TDS_OK;
+}
+
+// Theorem 2's interface values from the beta weights, in the plan's order
+hipError_t run_iface(tds_plan* h, const Work& w, double* xsep, int64_t N, hipStream_t s) {
+    if (h->iface == TDS_IFACE_DICHOTOMY)
+        return launch_iface_dichotomy(h->dev, w.betaR, w.betaL, w.SR, w.SL, xsep, N, s);
+    return launch_iface(h->dev, w.betaR, w.betaL, xsep, N, s);
 }
 
 hipEvent_t* timing_slot(tds_plan* h) {
@@ -234,19 +260,17 @@ hipEvent_t* timing_slot(tds_plan* h) {
 int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hipStream_t s,
                 int sweep_mode) {
     const DevTables& t = h->dev;
-    const int64_t P = t.P;
-    const size_t nb = align256(sizeof(double) * (size_t)P * (size_t)N);
-    int rc = ensure_work(h, 2 * nb + align256(sizeof(double) * (size_t)(P > 1 ? P - 1 : 1) * N));
+    Work w;
+    int rc = take_work(h, N, w);
     if (rc) return rc;
-    double* betaR = (double*)general_of(h);
-    double* betaL = (double*)(general_of(h) + nb);
-    double* xsep = (double*)(general_of(h) + 2 * nb);
+    double* xsep = w.xsep;
     hipEvent_t* ev = timing_slot(h);
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TDS_EHIP;
     if (t.P >= 2) {
-        if (launch_beta(t, F, mode != TDS_F64, N, betaR, betaL, s) != hipSuccess) return TDS_EHIP;
+        if (launch_beta(t, F, mode != TDS_F64, N, w.betaR, w.betaL, s) != hipSuccess)
+            return TDS_EHIP;
         if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TDS_EHIP;
-        if (launch_iface(t, betaR, betaL, xsep, N, s) != hipSuccess) return TDS_EHIP;
+        if (run_iface(h, w, xsep, N, s) != hipSuccess) return TDS_EHIP;
     } else if (ev && hipEventRecord(ev[1], s) != hipSuccess) {
         return TDS_EHIP;
     }
@@ -334,12 +358,14 @@ int tdsolve_components(tds_handle h, const void* F, double* Xsep, int64_t N, int
     if (rc) return rc;
     if (N == 0 || h->dev.P < 2) return TDS_OK;
     if (!F || !Xsep) return TDS_EINVAL;
-    const size_t nb = align256(sizeof(double) * (size_t)h->dev.P * (size_t)N);
-    rc = ensure_work(h, nb * 2);
+    Work w;
+    rc = take_work(h, N, w);
     if (rc) return rc;
-    double* betaR = (double*)general_of(h);
-    double* betaL = (double*)(general_of(h) + nb);
-    return interface_step(h, F, N, mode, Xsep, betaR, betaL, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_beta(h->dev, F, mode != TDS_F64, N, w.betaR, w.betaL, s) != hipSuccess)
+        return TDS_EHIP;
+    if (run_iface(h, w, Xsep, N, s) != hipSuccess) return TDS_EHIP;
+    return TDS_OK;
 }
 
 int tdsolve_backward(tds_handle h, const void* X, const void* gX, void* gF, double* ga,
@@ -424,6 +450,13 @@ int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls) {
     }
     if (calls) *calls = (int64_t)ncalls;
     h->events_used = 0;
+    return TDS_OK;
+}
+
+int tdsolve_set_interface(tds_handle h, int32_t order) {
+    if (!h || h->is_batch) return TDS_EINVAL;
+    if (order != TDS_IFACE_RECURRENCE && order != TDS_IFACE_DICHOTOMY) return TDS_EINVAL;
+    h->iface = order;
     return TDS_OK;
 }
 

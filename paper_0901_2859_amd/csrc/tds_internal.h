@@ -81,6 +81,11 @@ hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N,
 hipError_t launch_iface(const DevTables& t, const double* betaR,
                         const double* betaL, double* xsep, int64_t N,
                         hipStream_t s);
+// the interface step by the dichotomy (Algorithm 4); SR, SL: work arrays
+// of (P + 1) x N doubles
+hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR,
+                                  const double* betaL, double* SR, double* SL,
+                                  double* xsep, int64_t N, hipStream_t s);
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         int mode, int passes, const double* xsep,
                         hipStream_t s);

@@ -154,6 +154,54 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
 // once; otherwise S^R is written to xsep and S^L added after a barrier.
 constexpr int kScanMaxGroups = 16;
 constexpr int kScanMaxPer = 8;     // beta values a thread keeps in registers
+constexpr int kChainChunk = 8;     // beta values read per memory round trip
+
+// S^R recurrence y <- rho_j y + beta^R_j for j = j0 .. j1-1 (rho_0 is not
+// used: S^R_0 = 0), reading kChainChunk values per round trip; every y is
+// stored to out[j] when out is given.
+__device__ __forceinline__ double chain_right(double y, const cptr<double> rho,
+                                              const double* __restrict__ beta, int64_t N,
+                                              int64_t n, int32_t j0, int32_t j1,
+                                              double* __restrict__ out) {
+    for (int32_t jb = j0; jb < j1; jb += kChainChunk) {
+        double v[kChainChunk];
+#pragma unroll
+        for (int u = 0; u < kChainChunk; ++u)
+            v[u] = (jb + u < j1) ? beta[(int64_t)(jb + u) * N + n] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kChainChunk; ++u) {
+            const int32_t j = jb + u;
+            if (j < j1) {
+                y = fma((j > 0) ? rho[j] : 0.0, y, v[u]);
+                if (out) out[(int64_t)j * N + n] = y;
+            }
+        }
+    }
+    return y;
+}
+
+// S^L recurrence z <- beta^L_j + lam_j z for j = j1 down to j0+1 (lam_{P-1}
+// is not used: S^L_P = 0); with out given, z is added to out[j-1].
+__device__ __forceinline__ double chain_left(double z, const cptr<double> lam, int32_t P,
+                                             const double* __restrict__ beta, int64_t N,
+                                             int64_t n, int32_t j1, int32_t j0,
+                                             double* __restrict__ out) {
+    for (int32_t jb = j1; jb > j0; jb -= kChainChunk) {
+        double v[kChainChunk];
+#pragma unroll
+        for (int u = 0; u < kChainChunk; ++u)
+            v[u] = (jb - u > j0) ? beta[(int64_t)(jb - u) * N + n] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kChainChunk; ++u) {
+            const int32_t j = jb - u;
+            if (j > j0) {
+                z = fma((j < P - 1) ? lam[j] : 0.0, z, v[u]);
+                if (out) out[(int64_t)(j - 1) * N + n] += z;
+            }
+        }
+    }
+    return z;
+}
 
 struct ScanLDS {
     double carry[2][kScanMaxGroups][kScanRhs];
@@ -200,10 +248,8 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
                 if (jb > b0) zl = fma((jb < P - 1) ? lam[jb] : 0.0, zl, bLv[u]);
             }
         } else {
-            for (int32_t j = f0; j < f1; ++j)
-                yl = fma((j > 0) ? rho[j] : 0.0, yl, betaR[(int64_t)j * N + n]);
-            for (int32_t j = b1; j > b0; --j)
-                zl = fma((j < P - 1) ? lam[j] : 0.0, zl, betaL[(int64_t)j * N + n]);
+            yl = chain_right(yl, rho, betaR, N, n, f0, f1, nullptr);
+            zl = chain_left(zl, lam, P, betaL, N, n, b1, b0, nullptr);
         }
     }
     if (g < kScanMaxGroups) {
@@ -233,10 +279,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
                 }
             }
         } else {
-            for (int32_t j = f0; j < f1; ++j) {
-                y = fma((j > 0) ? rho[j] : 0.0, y, betaR[(int64_t)j * N + n]);
-                xsep[(int64_t)j * N + n] = y;
-            }
+            chain_right(y, rho, betaR, N, n, f0, f1, xsep);
         }
     }
     __syncthreads();     // S^R of every group is in LDS or xsep (same workgroup)
@@ -252,11 +295,62 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             }
         }
     } else {
-        for (int32_t j = b1; j > b0; --j) {
-            z = fma((j < P - 1) ? lam[j] : 0.0, z, betaL[(int64_t)j * N + n]);
-            xsep[(int64_t)(j - 1) * N + n] += z;       // x(s_j) = S^R_j + S^L_j
-        }
+        chain_left(z, lam, P, betaL, N, n, b1, b0, xsep);   // x(s_j) = S^R_j + S^L_j
     }
+}
+
+// ==========================================================================
+// Interface step by the dichotomy (Algorithm 4 step 2.2, Theorem 3,
+// eq. omega_i).  The p = P-1 interface rows are found level by level:
+// level l = 1 .. floor(log2 p) + 1 takes the rows i = step (2m + 1) <= p,
+// step = 2^(levels - l); the nearest interface rows already known are
+// k1 = i - step (0: the left end of the domain) and k2 = i + step (P, the
+// right end, when past p).  Between them the two partial sums continue from
+// the known ones (the reading of Theorem 3's correction terms):
+//     S^R_i from S^R_{k1} by S^R_{j+1} = rho_j S^R_j + beta^R_j, j = k1..i-1,
+//     S^L_i from S^L_{k2} by S^L_j = beta^L_j + lam_j S^L_{j+1}, j = k2-1..i,
+// and x(s_i) = S^R_i + S^L_i.  Rows of one level are independent (the
+// remark after Algorithm 4): they are spread over the workgroup's four row
+// slots, its 64 lanes being 64 right-hand sides, and the levels are
+// separated by workgroup barriers.  S^R and S^L are kept in work arrays of
+// (P + 1) x N each.  The same values as the recurrences of k_iface up to
+// rounding; O(P log P) work per right-hand side instead of O(P).
+constexpr int kDichRhs = 64;
+constexpr int kDichSlots = kWG / kDichRhs;
+
+__global__ __launch_bounds__(kWG) void k_iface_dich(DevTables T, int64_t N,
+                                                   const double* __restrict__ betaR,
+                                                   const double* __restrict__ betaL,
+                                                   double* SR, double* SL,
+                                                   double* __restrict__ xsep) {
+    const int32_t P = T.P;
+    const int32_t p = P - 1;
+    const int lane = threadIdx.x % kDichRhs;
+    const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x / kDichRhs);
+    const int64_t n = (int64_t)blockIdx.x * kDichRhs + lane;
+    const bool live = n < N;
+    const cptr<double> rho = cst(T.rho), lam = cst(T.lam);
+    int levels = 0;
+    while ((int64_t(1) << levels) <= p) ++levels;          // floor(log2 p) + 1
+    for (int l = 1; l <= levels; ++l) {
+        const int32_t step = 1 << (levels - l);
+        for (int32_t m = slot;; m += kDichSlots) {
+            const int32_t i = step * (2 * m + 1);
+            if (i > p) break;
+            if (!live) continue;
+            const int32_t k1 = i - step, k2 = (i + step <= p) ? i + step : P;
+            double sr = (k1 == 0) ? 0.0 : SR[(int64_t)k1 * N + n];
+            sr = chain_right(sr, rho, betaR, N, n, k1, i, nullptr);
+            double sl = (k2 == P) ? 0.0 : SL[(int64_t)k2 * N + n];
+            sl = chain_left(sl, lam, P, betaL, N, n, k2 - 1, i - 1, nullptr);
+            SR[(int64_t)i * N + n] = sr;
+            SL[(int64_t)i * N + n] = sl;
+        }
+        __syncthreads();        // this level's sums are the next level's k1, k2
+    }
+    if (!live) return;
+    for (int32_t k = 1 + slot; k <= p; k += kDichSlots)
+        xsep[(int64_t)(k - 1) * N + n] = SR[(int64_t)k * N + n] + SL[(int64_t)k * N + n];
 }
 
 // ==========================================================================
@@ -628,6 +722,15 @@ hipError_t launch_iface(const DevTables& t, const double* betaR, const double* b
     scan_shape(t.P, &per, &G);
     hipLaunchKernelGGL(k_iface, dim3((unsigned)((N + kScanRhs - 1) / kScanRhs)),
                        dim3(kScanRhs * G), 0, s, t, N, per, G, betaR, betaL, xsep);
+    return hipGetLastError();
+}
+
+hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR, const double* betaL,
+                                  double* SR, double* SL, double* xsep, int64_t N,
+                                  hipStream_t s) {
+    if (t.P < 2 || N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iface_dich, dim3((unsigned)((N + kDichRhs - 1) / kDichRhs)), dim3(kWG),
+                       0, s, t, N, betaR, betaL, SR, SL, xsep);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ SYMBOLS = [
     "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
-    "tdsolve_prepare_host_general",
+    "tdsolve_prepare_host_general", "tdsolve_set_interface",
 ]
 
 _lib = None
@@ -68,6 +68,7 @@ def lib():
     L.tdsolve_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp]
     L.tdsolve_residual.argtypes = [vp, vp, vp, i64, i32, vp, vp]
     L.tdsolve_set_refinement.argtypes = [vp, i32]
+    L.tdsolve_set_interface.argtypes = [vp, i32]
     L.tdsolve_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.tdsolve_prepare_host.argtypes = [dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
     L.tdsolve_prepare_host_general.argtypes = [dp, dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
@@ -205,6 +206,12 @@ class Plan:
         calls = np.zeros(1, dtype=np.int64)
         _check(lib().tdsolve_timing_read(self._h, _ptr(ms), _ptr(calls)), "tdsolve_timing_read")
         return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
+
+    def set_interface(self, order: str):
+        """'recurrence' (default, Theorem 2 as two recurrences) or
+        'dichotomy' (Algorithm 4, level by level)."""
+        code = {"recurrence": 0, "dichotomy": 1}[order]
+        _check(lib().tdsolve_set_interface(self._h, code), "tdsolve_set_interface")
 
     def set_refinement(self, passes: int):
         _check(lib().tdsolve_set_refinement(self._h, int(passes)), "tdsolve_set_refinement")
