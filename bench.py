@@ -11,8 +11,10 @@ sets are rotated so that consecutive steps do not find their data in the
 
 Other workloads (--workload): `adi` (8192 x 8192 ADI line solves, P = 128),
 `batch` (256 matrices of uneven sizes and series lengths, one launch per
-step of the method, block counts from the batch autotuner) and `gradient`
-(2048 x 1024, one step = forward solve + adjoint: gF, ga, gb).  The
+step of the method, block counts from the batch autotuner), `gradient`
+(2048 x 1024, one step = forward solve + adjoint: gF, ga, gb) and `fourier`
+(a series of 256 2-D Poisson problems on a 1024 x 1024 mesh by the variable
+separation method: sine transforms plus 1023 tridiagonal series).  The
 preliminary step (host FP64 tables + upload) is timed separately
 (`prepare_ms`).
 
@@ -46,11 +48,12 @@ def parse():
     p.add_argument("--mode", default="f32_refined",
                    choices=["f32_refined", "f64", "f32_wide", "f32"])
     p.add_argument("--workload", default="poisson",
-                   choices=["poisson", "adi", "batch", "gradient"],
+                   choices=["poisson", "adi", "batch", "gradient", "fourier"],
                    help="poisson: 1-D Poisson series 4096x4096, P=64 (default); "
                         "adi: ADI line solves 8192x8192, b=2.05, P=128; "
                         "batch: 256 uneven matrices, autotuned block counts; "
-                        "gradient: 2048x1024 forward + adjoint, P=32")
+                        "gradient: 2048x1024 forward + adjoint, P=32; "
+                        "fourier: series of 256 2-D Poisson problems on a 1024^2 mesh")
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
@@ -291,6 +294,68 @@ class Gradient(Single):
         return r
 
 
+class Fourier:
+    """Series of S 2-D Poisson problems by the variable separation method."""
+
+    def __init__(self, args, t, wl, torch):
+        from paper_0901_2859_amd.fourier import FourierPoisson2D
+        self.args, self.t, self.torch = args, t, torch
+        self.n = args.M or 1024
+        self.S = args.N or 256
+        self.unknowns = self.S * (self.n - 1) ** 2
+        self.name = (f"variable separation (Fourier) method: {self.S} 2-D Poisson problems "
+                     f"on a {self.n}x{self.n} mesh, 5-point operator, uniform random sources")
+        self.config = {"workload": self.name, "mesh": self.n, "problems": self.S}
+        self.cls = FourierPoisson2D
+        self.solvers = {}
+        t0 = time.perf_counter()
+        self.solver(args.mode)
+        torch.cuda.synchronize()
+        self.prepare_ms = (time.perf_counter() - t0) * 1e3
+        self.P = self.solvers[args.mode].P
+
+    def solver(self, mode):
+        if mode not in self.solvers:
+            self.solvers[mode] = self.cls(self.n, self.n, self.S, mode=mode)
+        return self.solvers[mode]
+
+    def sweep_bytes(self, mode):
+        M, N = self.n - 1, self.S
+        return sum(M * N * (F_BYTES[mode] + X_BYTES[mode]) + 2 * (p - 1) * N * 8 for p in self.P)
+
+    def run(self, mode, steps, warmup):
+        torch = self.torch
+        import numpy as np
+        fp = self.solver(mode)
+        rng = np.random.default_rng(6)
+        f = torch.from_numpy(rng.uniform(-1, 1, size=(self.S, self.n - 1, self.n - 1))).cuda()
+        if mode != "f64":
+            f = f.float()
+
+        def solve(k):
+            fp.solve(f)
+
+        r = time_steps(solve, 1, steps, warmup, self.args.graph, fp.plan, torch)
+        r["eta_max"], r["r2_max"], r["sets"] = None, None, 1
+        return r
+
+    def cpu_baseline(self, seconds):
+        import numpy as np
+        from oracle import poisson2d
+        import oracle
+        rng = np.random.default_rng(6)
+        h = 1.0 / self.n
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds and done < self.S:
+            poisson2d.solve_direct(rng.uniform(-1, 1, size=(self.n - 1, self.n - 1)), h, h)
+            done += 1
+        el = time.perf_counter() - t0
+        return {"value": done * (self.n - 1) ** 2 / el, "unit": "unknowns/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"direct sparse LU of the 5-point problem, {done} of the "
+                          f"{self.S} problems in {el:.1f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -312,7 +377,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    W = {"batch": Batch, "gradient": Gradient}.get(args.workload, Single)(args, t, wl, torch)
+    W = {"batch": Batch, "gradient": Gradient, "fourier": Fourier}.get(
+        args.workload, Single)(args, t, wl, torch)
 
     def run(mode, steps, warmup):
         r = W.run(mode, steps, warmup)
@@ -327,9 +393,9 @@ def main():
     sweep_bytes = W.sweep_bytes(args.mode)
     ms_sweep = main_r["ms_sweep"]
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
-    kname = "k_sweep_batch" if args.workload == "batch" else "k_sweep_reg"
-    shape = ("batch" if args.workload == "batch"
-             else f"{args.workload}_{W.M}x{W.N}_P{W.P}")
+    batched = args.workload in ("batch", "fourier")
+    kname = "k_sweep_batch" if batched else "k_sweep_reg"
+    shape = (args.workload if batched else f"{args.workload}_{W.M}x{W.N}_P{W.P}")
     # HBM bytes per launch measured by rocprofv3 counters for this kernel,
     # mode and workload; null unless taken from the current kernel sources
     tr = profdigest.read_traffic(os.path.join(

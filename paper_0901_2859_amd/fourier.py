@@ -1,0 +1,102 @@
+"""Application driver: a series of 2-D Poisson problems by the variable
+separation (Fourier) method on top of the uneven-batch solver.
+
+The paper's section "Variable separation method": on an N1 x N2 mesh with
+steps h1, h2 and zero boundary values, -Delta u = f_n (n = 1..S problems on
+the same mesh) is expanded in the eigenfunctions sin(pi l j / N2) of the
+difference operator in y; harmonic l then obeys, for every problem n, the
+tridiagonal system (eq. SLAU_FFT, here multiplied by -1)
+
+    (2 + d_l) u_i(l) - u_{i-1}(l) - u_{i+1}(l) = h1^2 f_i(l),  i = 1..N1-1,
+    d_l = 4 (h1 / h2)^2 sin^2(pi l / (2 N2)),               (eq. series_fft)
+
+one fixed matrix per harmonic with S right-hand sides (eq. poisson_end):
+N2-1 series of the kind the library solves, handed to it as one batch.  The
+sine transforms along y are FFTs of the odd extension (torch.fft); the
+transposes that bring the S problems next to each other (RHS-interleaved
+layout per harmonic) are torch copies.  Only the tridiagonal series run in
+the library's kernels.
+
+Layout: f and u are (S, N1-1, N2-1) device tensors, u[n, i-1, j-1] = u_n at
+mesh point (i, j).
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import tdsolve as t
+
+
+def dst1(x):
+    """Type-I sine transform along the last axis: y_l = sum_j x_j
+    sin(pi l j / (m + 1)), l, j = 1..m, via the FFT of the odd extension of
+    length 2 (m + 1)."""
+    import torch
+    m = x.shape[-1]
+    z = torch.zeros(x.shape[:-1] + (1,), dtype=x.dtype, device=x.device)
+    ext = torch.cat([z, x, z, -torch.flip(x, dims=[-1])], dim=-1)
+    return -torch.fft.rfft(ext, dim=-1).imag[..., 1:m + 1] / 2
+
+
+class FourierPoisson2D:
+    """Series of S Poisson problems -Delta u = f on an N1 x N2 mesh of the
+    rectangle [0, N1 h1] x [0, N2 h2], zero Dirichlet boundary values.
+
+    mode: the library's solve mode for the per-harmonic series ("f64",
+    "f32_refined", "f32_wide", "f32"); the transforms run in FP64 for "f64"
+    and FP32 otherwise.  P: blocks per harmonic matrix (None: the batch
+    autotuner's choice for S right-hand sides)."""
+
+    def __init__(self, N1: int, N2: int, S: int, h1: float = None, h2: float = None,
+                 mode: str = "f64", P: Optional[int] = None, autotune_cache: bool = True):
+        if N1 < 2 or N2 < 2 or S < 1:
+            raise ValueError("need N1, N2 >= 2 and S >= 1")
+        self.N1, self.N2, self.S = N1, N2, S
+        self.h1 = h1 if h1 is not None else 1.0 / N1
+        self.h2 = h2 if h2 is not None else 1.0 / N2
+        self.mode = mode
+        M = N1 - 1
+        L = N2 - 1
+        ratio = (self.h1 / self.h2) ** 2
+        l = np.arange(1, L + 1)
+        self.d = 4.0 * ratio * np.sin(np.pi * l / (2 * N2)) ** 2          # eq. series_fft
+        a = np.full(M - 1, -1.0)
+        self._a = [a] * L
+        self._b = [np.full(M, 2.0 + dl) for dl in self.d]
+        if P is None:
+            Ps, _ = t.batch_autotune(self._a, self._b, [S] * L, mode, cache=autotune_cache)
+        else:
+            Ps = [P] * L
+        self.P = Ps
+        self.plan = t.BatchPlan(self._a, self._b, Ps)
+
+    def solve(self, f, stream=None):
+        """u for the S right-hand sides f, shape (S, N1-1, N2-1)."""
+        import torch
+        S, M, L = self.S, self.N1 - 1, self.N2 - 1
+        if tuple(f.shape) != (S, M, L):
+            raise ValueError(f"f must have shape {(S, M, L)}")
+        wdt = torch.float64 if self.mode == "f64" else torch.float32
+        # harmonics of f along y, scaled to the right-hand side h1^2 f~(l)
+        scale = self.h1 ** 2 * 2.0 / self.N2
+        fl = dst1(f.to(wdt)) * scale                          # (S, i, l)
+        rhs = fl.permute(2, 1, 0).contiguous()               # (l, i, S): RHS-interleaved
+        X = self.plan.solve_stacked(rhs, mode=self.mode, stream=stream)
+        ul = X.permute(2, 1, 0)                               # (S, i, l)
+        return dst1(ul.contiguous())                          # back to mesh values in y
+
+    @staticmethod
+    def eigen_rhs(N1, N2, k, l, h1=None, h2=None):
+        """(f, u) of one discrete eigenfunction sin(pi k i/N1) sin(pi l j/N2):
+        the exact discrete solution is f divided by its eigenvalue."""
+        h1 = h1 if h1 is not None else 1.0 / N1
+        h2 = h2 if h2 is not None else 1.0 / N2
+        i = np.arange(1, N1)[:, None]
+        j = np.arange(1, N2)[None, :]
+        phi = np.sin(math.pi * k * i / N1) * np.sin(math.pi * l * j / N2)
+        lam = 4 / h1 ** 2 * math.sin(math.pi * k / (2 * N1)) ** 2 + \
+            4 / h2 ** 2 * math.sin(math.pi * l / (2 * N2)) ** 2
+        return phi, phi / lam

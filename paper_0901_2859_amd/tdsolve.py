@@ -358,6 +358,31 @@ class BatchPlan:
                "tdsolve_batch_series")
         return X_list
 
+    def solve_stacked(self, F, X=None, mode="f32_refined", stream=None):
+        """The batch with every matrix of the same size M and the same series
+        length N, given as one contiguous (K, M, N) tensor (matrix k's
+        right-hand sides in F[k]); returns X of the same shape."""
+        import torch
+        m = mode_id(mode)
+        if not (F.is_cuda and F.dim() == 3 and F.shape[0] == self.K and F.is_contiguous()
+                and F.dtype == getattr(torch, _F_DTYPE[m])):
+            raise ValueError(f"F must be a contiguous (K, M, N) {_F_DTYPE[m]} device tensor")
+        K, M, N = F.shape
+        if any(mk != M for mk in self.M):
+            raise ValueError("solve_stacked needs matrices of one size")
+        if X is None:
+            X = torch.empty((K, M, N), dtype=getattr(torch, _X_DTYPE[m]), device=F.device)
+        elif not (X.is_cuda and tuple(X.shape) == (K, M, N) and X.is_contiguous()
+                  and X.dtype == getattr(torch, _X_DTYPE[m])):
+            raise ValueError("X must match F")
+        k = np.arange(K, dtype=np.uint64)
+        Fp = (F.data_ptr() + k * np.uint64(M * N * F.element_size())).astype(np.uint64)
+        Xp = (X.data_ptr() + k * np.uint64(M * N * X.element_size())).astype(np.uint64)
+        Ns = np.full(K, N, dtype=np.int64)
+        _check(lib().tdsolve_batch_series(self._h, _ptr(Fp), _ptr(Xp), _ptr(Ns), m,
+                                          _stream_ptr(stream)), "tdsolve_batch_series")
+        return X
+
     def close(self):
         if getattr(self, "_h", None):
             lib().tdsolve_destroy(self._h)

@@ -301,3 +301,34 @@ def test_tridiag_general_manufactured_integer_solution():
     f[1:] += lower[1:] * x_true[:-1]
     f[:-1] += upper[:-1] * x_true[1:]
     assert np.allclose(oracle.tridiag_general(lower, diag, upper, f), x_true, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------- 2-D Poisson (direct)
+def test_poisson2d_direct_discrete_eigenfunction():
+    # sin(pi k i/N1) sin(pi l j/N2) is an eigenvector of the 5-point operator
+    # with eigenvalue 4/h1^2 sin^2(pi k/2N1) + 4/h2^2 sin^2(pi l/2N2)
+    from oracle import poisson2d
+    N1, N2, h1, h2 = 24, 17, 0.1, 0.07
+    i = np.arange(1, N1)[:, None]
+    j = np.arange(1, N2)[None, :]
+    for k, l in ((1, 1), (5, 3), (23, 16)):
+        phi = np.sin(np.pi * k * i / N1) * np.sin(np.pi * l * j / N2)
+        lam = 4 / h1 ** 2 * np.sin(np.pi * k / (2 * N1)) ** 2 + \
+            4 / h2 ** 2 * np.sin(np.pi * l / (2 * N2)) ** 2
+        u = poisson2d.solve_direct(phi, h1, h2)
+        assert np.allclose(u, phi / lam, rtol=0, atol=1e-12 * np.max(np.abs(phi / lam)))
+
+
+def test_poisson2d_direct_manufactured_second_order():
+    # u = sin(2 pi x) sin(2 pi y), -Delta u = 8 pi^2 u on the unit square
+    # (the paper's test problem): the discrete error falls 4x per halving of h
+    from oracle import poisson2d
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / n
+        x = np.arange(1, n)[:, None] * h
+        y = np.arange(1, n)[None, :] * h
+        ue = np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+        u = poisson2d.solve_direct(8 * np.pi ** 2 * ue, h, h)
+        errs.append(np.max(np.abs(u - ue)))
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.8 < errs[1] / errs[2] < 4.2, errs
