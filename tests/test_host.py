@@ -222,3 +222,10 @@ def test_prepare_general_errors_without_gpu():
     nan = lo.copy(); nan[0] = np.nan
     assert L.tdsolve_prepare_general(P_(nan), P_(d), P_(up), 10, 2, ctypes.byref(h)) == -1
     assert L.tdsolve_prepare_general(None, P_(d), P_(up), 10, 2, ctypes.byref(h)) == -1
+
+
+def test_adi_iteration_count_formula():
+    # eq. ocenka1: n0 = 0.2 ln(4N/pi) ln(4/eps); N = 64, eps = 1e-6 gives 13.4
+    from paper_0901_2859_amd.adi import n0_iterations
+    assert n0_iterations(64, 1e-6) == 14
+    assert n0_iterations(1024, 1e-5) == int(np.ceil(0.2 * np.log(4096 / np.pi) * np.log(4e5)))
