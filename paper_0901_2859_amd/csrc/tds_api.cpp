@@ -582,7 +582,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         d.T = t;
         d.item0 = items;
         d.scan0 = scans;
-        scan_shape(t.P, &d.per, &d.G);
+        scan_shape(t.P, kScanBatchGroups, &d.per, &d.G);
         const size_t nb = align256(sizeof(double) * (size_t)t.P * (size_t)n);
         d.betaR = (double*)bytes;
         d.betaL = (double*)(bytes + nb);

@@ -13,6 +13,7 @@ namespace tds {
 // lane one right-hand side.
 constexpr int kWG = 256;
 constexpr int kScanRhs = 16;      // right-hand sides per interface-scan workgroup
+constexpr int kScanBatchGroups = 16;   // scan groups per batch workgroup
 
 // Largest block (rows of one segment) handled by the register-resident
 // sweep; larger blocks take the streaming sweep, which keeps the forward
@@ -93,8 +94,9 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
 // register-sweep row bucket (32, 64, 128) of a largest block size, 0 if the
 // streaming sweep is needed
 int32_t rows_bucket(int32_t max_rows);
-// shape of the two-level interface scan: blocks per group, groups (<= 16)
-void scan_shape(int32_t P, int32_t* per, int32_t* G);
+// shape of the two-level interface scan: blocks per group, groups
+// (<= max_groups; 16 for the batch kernels)
+void scan_shape(int32_t P, int32_t max_groups, int32_t* per, int32_t* G);
 
 // One matrix of a batch: its tables, its series and its slices of the work
 // buffer, and where its work items start in the batch launches (item0: beta

@@ -152,7 +152,8 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
 // values in registers (per <= 8), S^R goes to LDS and the thread owning the
 // same interface row in the backward direction writes S^R + S^L to xsep
 // once; otherwise S^R is written to xsep and S^L added after a barrier.
-constexpr int kScanMaxGroups = 16;
+constexpr int kScanMaxGroups = kScanBatchGroups;   // batch workgroups (one shape for all)
+constexpr int kScanMaxGroupsSingle = 64;  // single-matrix workgroups (up to 1024 threads)
 constexpr int kScanMaxPer = 8;     // beta values a thread keeps in registers
 constexpr int kChainChunk = 8;     // beta values read per memory round trip
 
@@ -203,17 +204,19 @@ __device__ __forceinline__ double chain_left(double z, const cptr<double> lam, i
     return z;
 }
 
-struct ScanLDS {
-    double carry[2][kScanMaxGroups][kScanRhs];
-    double prod[2][kScanMaxGroups];
-    double sr[kScanMaxGroups * kScanMaxPer][kScanRhs];
-};
+// LDS of one interface-scan workgroup (G groups): the group carries
+// carry[2][G][kScanRhs], the products of the factors prod[2][G] and, when
+// the beta values stay in registers, S^R by interface row sr[G per][kScanRhs].
+__host__ __device__ constexpr size_t scan_lds_doubles(int32_t G, int32_t per) {
+    return (size_t)2 * G * kScanRhs + 2 * G +
+           (per <= kScanMaxPer ? (size_t)G * per * kScanRhs : 0);
+}
 
 __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_t per,
                                            int32_t G, const double* __restrict__ betaR,
                                            const double* __restrict__ betaL,
                                            double* __restrict__ xsep, int64_t sblk,
-                                           ScanLDS& S) {
+                                           double* smem) {
     const int32_t P = T.P;
     const int lane = threadIdx.x % kScanRhs;
     const int g = threadIdx.x / kScanRhs;
@@ -252,19 +255,22 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             zl = chain_left(zl, lam, P, betaL, N, n, b1, b0, nullptr);
         }
     }
-    if (g < kScanMaxGroups) {
-        S.carry[0][g][lane] = yl;
-        S.carry[1][g][lane] = zl;
+    double* carry = smem;                              // [2][G][kScanRhs]
+    double* prod = smem + 2 * G * kScanRhs;            // [2][G]
+    double* sr = prod + 2 * G;                          // [G per][kScanRhs]
+    if (grp) {
+        carry[g * kScanRhs + lane] = yl;
+        carry[(G + g) * kScanRhs + lane] = zl;
         if (lane == 0) {
-            S.prod[0][g] = pr;
-            S.prod[1][g] = pl;
+            prod[g] = pr;
+            prod[G + g] = pl;
         }
     }
     __syncthreads();
     double yin = 0.0, zin = 0.0;
     for (int q = 0; q < g && q < G; ++q) {
-        yin = fma(S.prod[0][q], yin, S.carry[0][q][lane]);
-        zin = fma(S.prod[1][q], zin, S.carry[1][q][lane]);
+        yin = fma(prod[q], yin, carry[q * kScanRhs + lane]);
+        zin = fma(prod[G + q], zin, carry[(G + q) * kScanRhs + lane]);
     }
     // finish the forward group: y_j = S^R_{j+1} into LDS or xsep
     if (live) {
@@ -275,7 +281,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
                 const int32_t j = f0 + u;
                 if (j < f1) {
                     y = fma((j > 0) ? rho[j] : 0.0, y, bRv[u]);
-                    S.sr[j][lane] = y;
+                    sr[j * kScanRhs + lane] = y;
                 }
             }
         } else {
@@ -291,7 +297,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             const int32_t j = b1 - u;
             if (j > b0) {
                 z = fma((j < P - 1) ? lam[j] : 0.0, z, bLv[u]);
-                xsep[(int64_t)(j - 1) * N + n] = S.sr[j - 1][lane] + z;   // S^R_j + S^L_j
+                xsep[(int64_t)(j - 1) * N + n] = sr[(j - 1) * kScanRhs + lane] + z;   // S^R_j + S^L_j
             }
         }
     } else {
@@ -585,11 +591,11 @@ __global__ __launch_bounds__(kWG) void k_beta(DevTables T, const Fin* __restrict
     beta_item<TMAX, Fin>(T, F, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, betaR, betaL, red);
 }
 
-__global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface(
+__global__ __launch_bounds__(kScanRhs * kScanMaxGroupsSingle) void k_iface(
     DevTables T, int64_t N, int32_t per, int32_t G, const double* __restrict__ betaR,
     const double* __restrict__ betaL, double* __restrict__ xsep) {
-    __shared__ ScanLDS S;
-    iface_item(T, N, per, G, betaR, betaL, xsep, (int64_t)blockIdx.x, S);
+    extern __shared__ double scan_smem[];
+    iface_item(T, N, per, G, betaR, betaL, xsep, (int64_t)blockIdx.x, scan_smem);
 }
 
 template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
@@ -649,7 +655,7 @@ __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict_
 
 __global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface_batch(
     const BatchDesc* __restrict__ D, int32_t K) {
-    __shared__ ScanLDS S;
+    __shared__ double S[scan_lds_doubles(kScanMaxGroups, kScanMaxPer)];
     const int64_t item = blockIdx.x;
     const int32_t k = find_desc(D, K, item, true);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
@@ -707,9 +713,9 @@ hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, d
     return hipGetLastError();
 }
 
-void scan_shape(int32_t P, int32_t* per, int32_t* G) {
+void scan_shape(int32_t P, int32_t max_groups, int32_t* per, int32_t* G) {
     const int32_t nsep = P > 1 ? P - 1 : 1;
-    int32_t p = (nsep + kScanMaxGroups - 1) / kScanMaxGroups;
+    int32_t p = (nsep + max_groups - 1) / max_groups;
     if (p < 4) p = 4;
     *per = p;
     *G = (nsep + p - 1) / p;
@@ -719,9 +725,10 @@ hipError_t launch_iface(const DevTables& t, const double* betaR, const double* b
                         double* xsep, int64_t N, hipStream_t s) {
     if (t.P < 2 || N == 0) return hipSuccess;
     int32_t per, G;
-    scan_shape(t.P, &per, &G);
+    scan_shape(t.P, kScanMaxGroupsSingle, &per, &G);
+    const size_t lds = sizeof(double) * scan_lds_doubles(G, per);
     hipLaunchKernelGGL(k_iface, dim3((unsigned)((N + kScanRhs - 1) / kScanRhs)),
-                       dim3(kScanRhs * G), 0, s, t, N, per, G, betaR, betaL, xsep);
+                       dim3(kScanRhs * G), lds, s, t, N, per, G, betaR, betaL, xsep);
     return hipGetLastError();
 }
 
