@@ -7,6 +7,9 @@
  *     A X_n = F_n,  n = 1..N,
  * with one constant, symmetric, nondegenerate tridiagonal M x M matrix A:
  * diagonal b[0..M-1], off-diagonal a[0..M-2], A[i][i+1] = A[i+1][i] = a[i].
+ * Non-symmetric tridiagonal matrices with A[i+1][i] A[i][i+1] > 0 are
+ * reduced to this case by a diagonal similarity (section "Nonsymmetrical
+ * matrices"; tdsolve_prepare_general).
  *
  * Method (section 3):
  *  - data decomposition (section 2): rows split into P contiguous blocks of
