@@ -165,6 +165,11 @@ class Single:
             self.plan.solve(Fs[k % n_sets], Xs[k % n_sets], mode=mode)
 
         r = time_steps(solve, n_sets, steps, warmup, args.graph, self.plan, torch)
+        if n_sets > 1:
+            # warm: one buffer set, which the last-level cache may hold
+            warm = time_steps(lambda k: self.plan.solve(Fs[0], Xs[0], mode=mode), 1,
+                              max(10, steps // 2), 3, args.graph, self.plan, torch)
+            r["warm_ms_per_step"] = warm["ms_per_step"]
         eta, r2 = self.plan.residual(Fs[0], Xs[0], mode=mode)
         torch.cuda.synchronize()
         r["eta_max"], r["r2_max"], r["sets"] = float(eta.max()), float(r2.max()), n_sets
@@ -435,6 +440,7 @@ def main():
         "phases_ms": {"beta": round(main_r["ms_beta"], 5),
                       "interface": round(main_r["ms_iface"], 5),
                       "sweep": round(main_r["ms_sweep"], 5)},
+        "warm_ms_per_step": main_r.get("warm_ms_per_step"),
         "r2_max": main_r["r2_max"],
         "eta_max": main_r["eta_max"],
         "prepare_ms": round(W.prepare_ms, 3),
