@@ -229,3 +229,21 @@ def test_adi_iteration_count_formula():
     from paper_0901_2859_amd.adi import n0_iterations
     assert n0_iterations(64, 1e-6) == 14
     assert n0_iterations(1024, 1e-5) == int(np.ceil(0.2 * np.log(4096 / np.pi) * np.log(4e5)))
+
+
+def test_new_entry_points_reject_bad_arguments_without_gpu():
+    # argument checks come before any HIP call
+    L = t.lib()
+    a, b = -np.ones(9), 3 * np.ones(10)
+    P_ = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    Pout = ctypes.c_int32()
+    ms = ctypes.c_double()
+    assert L.tdsolve_autotune(P_(a), P_(b), 10, 0, 0, 3, ctypes.byref(Pout), ctypes.byref(ms),
+                              None) == -1                              # N = 0
+    assert L.tdsolve_autotune(P_(a), P_(b), 10, 5, 9, 3, ctypes.byref(Pout), ctypes.byref(ms),
+                              None) == -1                              # bad mode
+    assert L.tdsolve_autotune(P_(a), P_(b), 10, 5, 0, 3, None, None, None) == -1
+    assert L.tdsolve_batch_autotune(0, None, None, None, None, 0, 3, None, None, None) == -1
+    assert L.tdsolve_set_interface(None, 1) == -1
+    assert L.tdsolve_prepare_host_general(P_(a), P_(b), None, 10, 2, None, None, None, None,
+                                          None, None) == -1
