@@ -231,7 +231,14 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a,
 /* F[k], X[k]: device pointers of matrix k's [M[k]][N[k]] arrays (element
  * types by `mode` as for tdsolve_series); the pointer arrays themselves are
  * host arrays of K entries.  N: host array of K counts (0 allowed).  All K
- * series are solved by one launch of each kernel. */
+ * series are solved by one launch of each kernel.  The per-matrix work
+ * descriptors are uploaded only when pointers or counts differ from the
+ * previous call, which synchronises `stream` (a host-to-device copy);
+ * repeating a call with the same arguments issues kernel launches only, so
+ * it can be captured in a HIP graph after one uncaptured call.
+ * Errors: TDS_EINVAL (null arrays or pointers, N[k] < 0, F[k] == X[k] with
+ * different element types), TDS_EUNSUPPORTED (more work items than one
+ * launch holds), TDS_ENOMEM, TDS_EHIP. */
 int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
                          const int64_t* N, int32_t mode, void* stream);
 
