@@ -61,6 +61,7 @@ def _check(X, ref, tol, what):
 @pytest.mark.parametrize("M,N,P,gamma", [
     (64, 16, 4, None), (300, 300, 10, None), (1000, 257, 16, None), (1000, 100, 13, None),
     (2000, 70, 2, None), (4096, 200, 64, 0.5), (1500, 90, 20, -0.8), (2, 3, 1, None),
+    (4096, 1100, 64, 0.3),   # 1152 tiles of 64 right-hand sides: some wavefronts take two
 ])
 def test_general_parity_all_modes(M, N, P, gamma):
     print(f"general M={M} N={N} P={P} gamma={gamma}", flush=True)

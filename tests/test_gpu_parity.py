@@ -216,6 +216,30 @@ def test_changing_n_and_graph_replays():
         _ = (F * 2).sum().item()
 
 
+@pytest.mark.parametrize("M,N,P,offset", [
+    # blocks of 62-64 rows: the refined sweep's pipelined kernel, whose
+    # wavefronts walk several tiles of 64 right-hand sides each
+    (2000, 4099, 32, 0),    # N % 4 != 0: 4-byte row loads, ragged last tile
+    (2000, 4100, 32, 0),    # 16-byte row loads except in the ragged last tile
+    (4096, 2048, 64, 0),    # full tiles, two per wavefront
+    (1000, 1024, 16, 1),    # F 4 bytes past a 16-byte boundary: 4-byte loads
+])
+def test_refined_many_tiles_per_wavefront(M, N, P, offset):
+    print(f"case M={M} N={N} P={P} offset={offset}", flush=True)
+    rng = np.random.default_rng(M + 7 * N + P)
+    a, b = _rand(rng, M)
+    F32 = rng.uniform(-1, 1, size=(M, N)).astype(np.float32)
+    Fw = F32.astype(np.float64)
+    ref = oracle.thomas(a, b, Fw)
+    plan = t.Plan(a, b, P)
+    buf = torch.empty(M * N + offset, dtype=torch.float32, device=DEV)
+    Fs = buf[offset:].view(M, N)
+    Fs.copy_(torch.from_numpy(F32))
+    assert (Fs.data_ptr() % 16 == 0) == (offset == 0)
+    X = plan.solve(Fs, mode="f32_refined").cpu().numpy()
+    _assert_parity(X, ref, _tol64(a, b, Fw, ref, P), "f32_refined")
+
+
 def test_bitwise_reproducible():
     rng = np.random.default_rng(3)
     M, N, P = 1000, 700, 16
