@@ -57,8 +57,10 @@ def parse():
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
-    p.add_argument("--interface", default="recurrence", choices=["recurrence", "dichotomy"],
-                   help="evaluation order of the interface values (single-matrix workloads)")
+    p.add_argument("--interface", default="dense", choices=["recurrence", "dichotomy", "dense"],
+                   help="evaluation order of the interface values (single-matrix workloads); "
+                        "dense: Theorem 2's double sum on the FP64 matrix cores, the fastest "
+                        "order measured at P <= 128")
     p.add_argument("--graph", action="store_true",
                    help="time replays of a captured HIP graph per step instead of eager launches")
     p.add_argument("--sets", type=int, default=0,

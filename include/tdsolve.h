@@ -168,10 +168,17 @@ int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
  *   TDS_IFACE_DICHOTOMY: Algorithm 4 (Theorem 3, eq. omega_i): the
  *     interface rows level by level, each from its nearest known
  *     neighbours, rows of one level in parallel; O(P log P) per
- *     right-hand side and a work area of 2 (P + 1) N doubles more.
- * Both give the same values up to rounding.  TDS_EINVAL for other values or
- * a batch handle. */
-enum { TDS_IFACE_RECURRENCE = 0, TDS_IFACE_DICHOTOMY = 1 };
+ *     right-hand side and a work area of 2 (P + 1) N doubles more;
+ *   TDS_IFACE_DENSE: Theorem 2's double sum (eq. theor_2) as one dense
+ *     product, Xsep = K [beta^R; beta^L], on the FP64 matrix cores, with
+ *     K ((P-1) x 2P: the ratio products between interface rows) built by
+ *     the call in FP64 and uploaded (about 16 P^2 bytes of device memory,
+ *     held until tdsolve_destroy); O(P^2) per right-hand side.  P <= 1024,
+ *     else TDS_EUNSUPPORTED; the call allocates and copies synchronously.
+ * All give the same values up to rounding.  TDS_EINVAL for other values or
+ * a batch handle; TDS_ENOMEM / TDS_EHIP if the dense table cannot be
+ * allocated or uploaded (the order is then unchanged). */
+enum { TDS_IFACE_RECURRENCE = 0, TDS_IFACE_DICHOTOMY = 1, TDS_IFACE_DENSE = 2 };
 int tdsolve_set_interface(tds_handle h, int32_t order);
 
 /* Number of refinement passes for TDS_F32_REFINED (0..8; default 2). */

@@ -20,6 +20,8 @@ struct tds_plan {
     double normA = 0.0;          // ||A||_inf
     int32_t passes = 2;          // refinement passes of TDS_F32_REFINED
     int32_t iface = TDS_IFACE_RECURRENCE;   // interface-step evaluation order
+    double* dense_K = nullptr;   // Theorem 2 coefficient table (TDS_IFACE_DENSE)
+    int32_t dense_Pc = 0, dense_Mr = 0;
     int device = 0;
     void* work = nullptr;        // grows with N
     size_t work_bytes = 0;
@@ -242,6 +244,9 @@ int take_work(tds_plan* h, int64_t N, Work& w) {
 hipError_t run_iface(tds_plan* h, const Work& w, double* xsep, int64_t N, hipStream_t s) {
     if (h->iface == TDS_IFACE_DICHOTOMY)
         return launch_iface_dichotomy(h->dev, w.betaR, w.betaL, w.SR, w.SL, xsep, N, s);
+    if (h->iface == TDS_IFACE_DENSE)
+        return launch_iface_dense(h->dense_K, h->dense_Pc, h->dense_Mr, h->dev.P, w.betaR,
+                                  w.betaL, xsep, N, s);
     return launch_iface(h->dev, w.betaR, w.betaL, xsep, N, s);
 }
 
@@ -455,7 +460,28 @@ int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls) {
 
 int tdsolve_set_interface(tds_handle h, int32_t order) {
     if (!h || h->is_batch) return TDS_EINVAL;
-    if (order != TDS_IFACE_RECURRENCE && order != TDS_IFACE_DICHOTOMY) return TDS_EINVAL;
+    if (order != TDS_IFACE_RECURRENCE && order != TDS_IFACE_DICHOTOMY &&
+        order != TDS_IFACE_DENSE)
+        return TDS_EINVAL;
+    if (order == TDS_IFACE_DENSE && !h->dense_K && h->host.P >= 2) {
+        if (h->host.P > kDenseMaxBlocks) return TDS_EUNSUPPORTED;
+        std::vector<double> Kt;
+        int32_t pc = 0, mr = 0;
+        const int rc = dense_interface_table(h->host, Kt, &pc, &mr);
+        if (rc) return rc;
+        void* d = nullptr;
+        const hipError_t e = hipMalloc(&d, sizeof(double) * Kt.size());
+        if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
+        if (e != hipSuccess) return TDS_EHIP;
+        if (hipMemcpy(d, Kt.data(), sizeof(double) * Kt.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            (void)hipFree(d);
+            return TDS_EHIP;
+        }
+        h->dense_K = (double*)d;
+        h->dense_Pc = pc;
+        h->dense_Mr = mr;
+    }
     h->iface = order;
     return TDS_OK;
 }
@@ -516,6 +542,10 @@ int tdsolve_destroy(tds_handle h) {
     if (h->dev_mem) (void)hipFree(h->dev_mem);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->d_desc) (void)hipFree(h->d_desc);
+    if (h->dense_K) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(h->dense_K);
+    }
     delete h;
     return TDS_OK;
 }

@@ -75,6 +75,14 @@ int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
 int host_prepare_general(const double* lo, const double* diag, const double* up,
                          int64_t M, int32_t P, HostTables& out);
 int32_t default_blocks(int64_t M);
+// Largest block count of the dense interface order: its table holds
+// 2 P (P-1) doubles (16 MB at 1024) and its work grows as P^2 per
+// right-hand side.
+constexpr int32_t kDenseMaxBlocks = 1024;
+// Theorem 2's coefficients as one matrix for the dense interface order
+// (layout in tds_prepare.cpp); Pc, Mr: padded part width and row count.
+int dense_interface_table(const HostTables& o, std::vector<double>& Kt, int32_t* Pc,
+                          int32_t* Mr);
 
 // Kernel launchers (tdsolve_kernels.hip).  All return hipError_t.
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N,
@@ -87,6 +95,11 @@ hipError_t launch_iface(const DevTables& t, const double* betaR,
 hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR,
                                   const double* betaL, double* SR, double* SL,
                                   double* xsep, int64_t N, hipStream_t s);
+// Theorem 2 as a dense product on the matrix cores (table from
+// dense_interface_table)
+hipError_t launch_iface_dense(const double* Kt, int32_t Pc, int32_t Mr, int32_t P,
+                              const double* betaR, const double* betaL, double* xsep, int64_t N,
+                              hipStream_t s);
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         int mode, int passes, const double* xsep,
                         hipStream_t s);

@@ -360,6 +360,76 @@ __global__ __launch_bounds__(kWG) void k_iface_dich(DevTables T, int64_t N,
 }
 
 // ==========================================================================
+// Interface values by Theorem 2's double sum (eq. theor_2) as one dense
+// product on the FP64 matrix cores:
+//     Xsep[k-1][n] = sum_j KR[k][j] beta^R_j[n] + sum_j KL[k][j] beta^L_j[n],
+// k = 1..P-1, with the ratio products KR[k][j] = rho_{j+1} ... rho_{k-1}
+// (j < k) and KL[k][j] = lam_k ... lam_{j-1} (j >= k) from the preliminary
+// step.  The coefficient table is k-major, Kt[kk][r] (output row r = k-1,
+// combined index kk = j for the right part, Pc + j for the left part;
+// Pc = P rounded up to 4, rows padded to Mr, a multiple of 64, zeros
+// elsewhere).
+//
+// Workgroup: 16 right-hand sides x 64 output rows, one wavefront per 16-row
+// tile.  A wavefront only visits the k-steps (4 values of j each) whose
+// coefficients are not all zero for its rows r = k-1: the right part up to
+// j = its last row (KR vanishes for j >= k), the left part from the step
+// holding its first k (KL vanishes for j < k).  It loads the operands of up
+// to 32 steps into registers at once (coefficients from the small table,
+// which stays in L2; beta values straight from memory), then chains the
+// steps' V_MFMA_F64_16X16X4F64 on one accumulator.  Operand layout of that
+// instruction (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[4 i + l / 16][l % 16] in element i (rows
+// interleaved across the four lane groups; checked by a probe on gfx950).
+constexpr int kDenseCols = 16;      // right-hand sides per workgroup
+constexpr int kDenseRows = 64;      // output rows per workgroup (4 tiles)
+constexpr int kDenseBatch = 32;     // k-steps whose operands are loaded together
+
+__global__ __launch_bounds__(kWG) void k_iface_dense(const double* __restrict__ Kt, int32_t Pc,
+                                                     int32_t Mr, int32_t P, int64_t N,
+                                                     const double* __restrict__ betaR,
+                                                     const double* __restrict__ betaL,
+                                                     double* __restrict__ xsep) {
+    using d4 = __attribute__((ext_vector_type(4))) double;
+    const int lane = threadIdx.x % 64;
+    const int tile = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int col = lane % 16, kq = lane / 16;
+    const int64_t n = (int64_t)blockIdx.x * kDenseCols + col;
+    const int32_t rlo = (int32_t)blockIdx.y * kDenseRows + 16 * tile;
+    if (rlo >= P - 1) return;                      // tile past the last interface row
+    const int32_t rhi = min(rlo + 15, P - 2);
+    // steps: right part j4 = 0, 4, .., <= rhi; left part j4 = (rlo + 1) & ~3, .., <= P-1
+    const int32_t nR = rhi / 4 + 1;
+    const int32_t jl0 = (rlo + 1) & ~3;
+    const int32_t nL = (P - 1 - jl0) / 4 + 1;
+    const int32_t steps = nR + nL;
+    const bool live = n < N;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t s0 = 0; s0 < steps; s0 += kDenseBatch) {
+        double av[kDenseBatch], bv[kDenseBatch];
+#pragma unroll
+        for (int u = 0; u < kDenseBatch; ++u) {
+            const int32_t st = s0 + u;
+            const bool left = st >= nR;
+            const int32_t j = left ? jl0 + 4 * (st - nR) + kq : 4 * st + kq;
+            const int32_t kk = left ? Pc + j : j;
+            const bool ok = st < steps && j < P;
+            av[u] = ok ? Kt[(int64_t)kk * Mr + rlo + col] : 0.0;
+            bv[u] = (ok && live) ? (left ? betaL : betaR)[(int64_t)j * N + n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kDenseBatch; ++u)
+            if (s0 + u < steps) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    if (!live) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int32_t r = rlo + 4 * i + kq;
+        if (r < P - 1) xsep[(int64_t)r * N + n] = acc[i];
+    }
+}
+
+// ==========================================================================
 // Block sweep, register-resident.  Block j's interior rows i0..i1 (block 0
 // starts at row 0; the others at the row after their left interface row)
 // are solved with x at the interface rows s_j (left, xl) and s_{j+1}
@@ -729,6 +799,17 @@ hipError_t launch_iface(const DevTables& t, const double* betaR, const double* b
     const size_t lds = sizeof(double) * scan_lds_doubles(G, per);
     hipLaunchKernelGGL(k_iface, dim3((unsigned)((N + kScanRhs - 1) / kScanRhs)),
                        dim3(kScanRhs * G), lds, s, t, N, per, G, betaR, betaL, xsep);
+    return hipGetLastError();
+}
+
+hipError_t launch_iface_dense(const double* Kt, int32_t Pc, int32_t Mr, int32_t P,
+                              const double* betaR, const double* betaL, double* xsep, int64_t N,
+                              hipStream_t s) {
+    if (P < 2 || N == 0) return hipSuccess;
+    if (Pc % 4 != 0 || Pc < P || Mr % kDenseRows != 0 || Mr < P - 1) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((N + kDenseCols - 1) / kDenseCols),
+                 (unsigned)((P - 1 + kDenseRows - 1) / kDenseRows), 1);
+    hipLaunchKernelGGL(k_iface_dense, g, dim3(kWG), 0, s, Kt, Pc, Mr, P, N, betaR, betaL, xsep);
     return hipGetLastError();
 }
 

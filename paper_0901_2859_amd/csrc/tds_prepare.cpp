@@ -264,4 +264,43 @@ int host_prepare_general(const double* lo, const double* diag, const double* up,
     return block_tables(o, o.l64.data(), o.a64.data());
 }
 
+// Theorem 2 (eq. theor_2) written out as one coefficient matrix: for the
+// interface rows k = 1..P-1,
+//     x(s_k) = sum_{j<k} Z^R(s_{j+1}, s_k) beta^R_j + sum_{j>=k} Z^L(s_j, s_k) beta^L_j,
+// where the ratio products between interface rows are the transfer factors
+// of the preliminary step, Z^R(s_{j+1}, s_k) = rho_{j+1} ... rho_{k-1} and
+// Z^L(s_j, s_k) = lam_k ... lam_{j-1} (each an empty product, 1, at j = k-1
+// and j = k respectively).  Layout k-major, Kt[kk][r] with r = k-1 and
+// kk = j (right part) or Pc + j (left part), Pc = P rounded up to 4, rows
+// padded to Mr = (P-1) rounded up to 64; every other entry is zero.
+int dense_interface_table(const HostTables& o, std::vector<double>& Kt, int32_t* Pc,
+                          int32_t* Mr) {
+    const int32_t P = o.P;
+    if (P < 2) return TDS_EINVAL;
+    const int32_t pc = (P + 3) / 4 * 4;
+    const int32_t mr = (P - 1 + 63) / 64 * 64;
+    const size_t kc = 2 * (size_t)pc;
+    try {
+        Kt.assign(kc * (size_t)mr, 0.0);
+    } catch (...) {
+        return TDS_ENOMEM;
+    }
+    for (int32_t k = 1; k <= P - 1; ++k) {
+        const size_t r = (size_t)(k - 1);
+        double z = 1.0;                          // Z^R(s_{j+1}, s_k), j = k-1 down to 0
+        for (int32_t j = k - 1; j >= 0; --j) {
+            Kt[(size_t)j * mr + r] = z;
+            if (j >= 1) z *= o.rho[j];
+        }
+        z = 1.0;                                 // Z^L(s_j, s_k), j = k up to P-1
+        for (int32_t j = k; j <= P - 1; ++j) {
+            Kt[((size_t)pc + j) * mr + r] = z;
+            if (j <= P - 2) z *= o.lam[j];
+        }
+    }
+    *Pc = pc;
+    *Mr = mr;
+    return TDS_OK;
+}
+
 }  // namespace tds

@@ -208,9 +208,10 @@ class Plan:
         return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
 
     def set_interface(self, order: str):
-        """'recurrence' (default, Theorem 2 as two recurrences) or
-        'dichotomy' (Algorithm 4, level by level)."""
-        code = {"recurrence": 0, "dichotomy": 1}[order]
+        """'recurrence' (default, Theorem 2 as two recurrences), 'dichotomy'
+        (Algorithm 4, level by level) or 'dense' (Theorem 2's double sum as
+        one product on the FP64 matrix cores; P <= 1024)."""
+        code = {"recurrence": 0, "dichotomy": 1, "dense": 2}[order]
         _check(lib().tdsolve_set_interface(self._h, code), "tdsolve_set_interface")
 
     def set_refinement(self, passes: int):

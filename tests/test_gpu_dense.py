@@ -1,0 +1,134 @@
+"""GPU: the interface step as Theorem 2's double sum (eq. theor_2) in one
+dense product on the FP64 matrix cores (tdsolve_set_interface(
+TDS_IFACE_DENSE)): against the oracle's literal double sum
+(oracle.method.interface_theor2), against the recurrence order, and end to
+end against the oracle's sweep.
+
+The cases cover one and several 64-row output groups, one and several
+128-wide k chunks (including chunks that hold the end of the right part and
+the start of the left part), P not a multiple of 4, ragged groups of 16
+right-hand sides, the largest P the order accepts, and a non-symmetric A.
+
+Tolerance: as in the parity tests, 1e-11 + 8 (t + 2P) u cond_n per
+right-hand side relative to its largest solution component; the dense sum
+adds at most 2P rounded terms, the bound of the recurrences' chains."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import method  # noqa: E402
+from paper_0901_2859_amd import tdsolve as t  # noqa: E402
+from paper_0901_2859_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _tol(a, b, F, ref, P):
+    tt, s = method.partition(len(b), P)
+    G = method.green_rows(a, b, s[1:P])
+    cond = (np.abs(G).T @ np.abs(F)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
+    return 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+
+
+@pytest.mark.parametrize("M,N,P", [(64, 16, 16), (300, 77, 10), (1024, 300, 64), (130, 5, 65),
+                                   (40, 9, 2), (90, 33, 3), (4096, 64, 128), (2000, 1000, 97),
+                                   (1200, 50, 300), (8192, 20, 1024)])
+def test_dense_components_match_oracle(M, N, P):
+    print(f"dense M={M} N={N} P={P}", flush=True)
+    w = wl.random_dominant(seed=M + 3 * P, M=M, N=N)
+    a, b, F = w["a"], w["b"], w["F"]
+    prep = method.prepare(a, b, P)
+    bR, bL = method.betas(prep, F)
+    xs_or = method.interface_theor2(prep, bR, bL)
+    ref = oracle.thomas(a, b, F)
+    tol = _tol(a, b, F, ref, P)
+    scale = np.max(np.abs(ref), axis=0)
+    plan = t.Plan(a, b, P)
+    Fd = torch.from_numpy(F).to(DEV)
+    plan.set_interface("dense")
+    xs_d = plan.components(Fd, mode="f64").cpu().numpy()
+    plan.set_interface("recurrence")
+    xs_r = plan.components(Fd, mode="f64").cpu().numpy()
+    e = np.max(np.abs(xs_d - xs_or), axis=0) / scale
+    assert np.all(e <= tol), ("dense vs oracle", e.max())
+    e = np.max(np.abs(xs_d - xs_r), axis=0) / scale
+    assert np.all(e <= tol), ("dense vs recurrence", e.max())
+
+
+def test_dense_full_solve_poisson_all_modes():
+    w = wl.poisson_series(M=4096, N=1000, P=64)
+    a, b, F32 = w["a"], w["b"], w["F"]
+    Fw = F32.astype(np.float64)
+    ref = oracle.thomas(a, b, Fw)
+    tol = _tol(a, b, Fw, ref, 64)
+    plan = t.Plan(a, b, 64)
+    plan.set_interface("dense")
+    Fs = torch.from_numpy(F32).to(DEV)
+    for mode, Fin in (("f64", Fs.double()), ("f32_refined", Fs), ("f32_wide", Fs)):
+        X = plan.solve(Fin, mode=mode).cpu().numpy()
+        e = np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)
+        assert np.all(e <= tol), (mode, e.max())
+
+
+def test_dense_general_matrix_matches_oracle():
+    # non-symmetric A: the transfer factors carry the similarity's ratios
+    rng = np.random.default_rng(5)
+    M, N, P = 1500, 70, 24
+    up = rng.uniform(0.2, 1.0, size=M - 1) * rng.choice([-1.0, 1.0], size=M - 1)
+    lo = np.sign(up) * rng.uniform(0.2, 1.0, size=M - 1)
+    d = (np.concatenate([[0], np.abs(lo)]) + np.concatenate([np.abs(up), [0]]) + 0.3) * \
+        rng.choice([-1.0, 1.0], size=M)
+    F = rng.uniform(-1, 1, size=(M, N))
+    low, upp = np.concatenate([[0.0], lo]), np.concatenate([up, [0.0]])
+    ref = np.stack([oracle.tridiag_general(low, d, upp, F[:, n]) for n in range(N)], 1)
+    plan = t.Plan.general(lo, d, up, P)
+    Fd = torch.from_numpy(F).to(DEV)
+    X_r = plan.solve(Fd, mode="f64").cpu().numpy()
+    plan.set_interface("dense")
+    X_d = plan.solve(Fd, mode="f64").cpu().numpy()
+    scale = np.max(np.abs(ref), axis=0)
+    assert np.max(np.abs(X_d - ref).max(axis=0) / scale) <= 1e-11
+    assert np.max(np.abs(X_d - X_r).max(axis=0) / scale) <= 1e-11
+
+
+def test_dense_limits_and_single_block():
+    a, b = -np.ones(4095), 3 * np.ones(4096)
+    plan = t.Plan(a, b, 1025)
+    with pytest.raises(t.TdsError) as err:
+        plan.set_interface("dense")
+    assert err.value.code == -6            # TDS_EUNSUPPORTED: P > 1024
+    # the order stays as it was and the plan still solves
+    F = torch.ones((4096, 3), dtype=torch.float64, device=DEV)
+    X = plan.solve(F, mode="f64").cpu().numpy()
+    assert np.allclose(X, oracle.thomas(a, b, np.ones((4096, 3))), rtol=1e-12, atol=0)
+    one = t.Plan(a[:99], b[:100], 1)          # no interface rows: nothing to build
+    one.set_interface("dense")
+    X1 = one.solve(F[:100].contiguous(), mode="f64").cpu().numpy()
+    assert np.allclose(X1, oracle.thomas(a[:99], b[:100], np.ones((100, 3))), rtol=1e-12)
+
+
+def test_dense_graph_replays_match_eager():
+    w = wl.random_dominant(seed=9, M=2048, N=700)
+    a, b, F = w["a"], w["b"], w["F"].astype(np.float32)
+    plan = t.Plan(a, b, 32)
+    plan.set_interface("dense")
+    Fs = torch.from_numpy(F).to(DEV)
+    X = torch.empty((2048, 700), dtype=torch.float64, device=DEV)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.solve(Fs, X, mode="f32_refined")
+    torch.cuda.synchronize()
+    ref = X.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.solve(Fs, X, mode="f32_refined")
+    for rep in range(3):
+        X.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref), rep
+        _ = (Fs * 2).sum().item()
