@@ -57,10 +57,11 @@ def parse():
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
-    p.add_argument("--interface", default="dense", choices=["recurrence", "dichotomy", "dense"],
+    p.add_argument("--interface", default="auto",
+                   choices=["auto", "recurrence", "dichotomy", "dense"],
                    help="evaluation order of the interface values (single-matrix workloads); "
-                        "dense: Theorem 2's double sum on the FP64 matrix cores, the fastest "
-                        "order measured at P <= 128")
+                        "auto: dense (Theorem 2's double sum on the FP64 matrix cores) for "
+                        "P <= 64, recurrence above, the faster order measured on each side")
     p.add_argument("--graph", action="store_true",
                    help="time replays of a captured HIP graph per step instead of eager launches")
     p.add_argument("--sets", type=int, default=0,
@@ -141,10 +142,12 @@ class Single:
         self.plan = t.Plan(self.a, self.b, P)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
-        self.plan.set_interface(args.interface)
+        order = args.interface
+        if order == "auto":
+            order = "dense" if P <= 64 else "recurrence"
+        self.plan.set_interface(order)
         self.unknowns = M * N
-        self.config = {"workload": self.name, "M": M, "N": N, "P": P,
-                       "interface": args.interface}
+        self.config = {"workload": self.name, "M": M, "N": N, "P": P, "interface": order}
 
     def sweep_bytes(self, mode):
         # the block sweep reads F, writes X, reads two interface values per

@@ -153,11 +153,14 @@ int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N,
                      int32_t mode, double* out, void* stream);
 
 /* Per-phase timing for measurement.  While enabled, every tdsolve_series
- * call on the handle records HIP events on its stream around its three
- * kernel phases.  tdsolve_timing_read waits for the last recorded event,
- * writes the accumulated milliseconds of [0] the beta weights, [1] the
- * interface step and [2] the block sweeps into ms (3 host doubles) and the
- * number of timed calls into *calls, then clears the record. */
+ * and tdsolve_batch_series call on the handle launches its three kernels
+ * with start and stop events (hipExtLaunchKernelGGL), which take each
+ * kernel's own start and end timestamps: the phases exclude the dispatch
+ * gaps between kernels.  tdsolve_timing_read waits for the last recorded
+ * event, writes the accumulated milliseconds of [0] the beta weights,
+ * [1] the interface step and [2] the block sweeps into ms (3 host doubles)
+ * and the number of timed calls into *calls, then clears the record.  Keep
+ * timing off while a stream is being captured into a graph. */
 int tdsolve_timing_enable(tds_handle h, int32_t on);
 int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
 

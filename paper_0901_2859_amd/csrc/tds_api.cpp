@@ -26,7 +26,8 @@ struct tds_plan {
     void* work = nullptr;        // grows with N
     size_t work_bytes = 0;
     bool timing = false;         // record per-phase events
-    std::vector<hipEvent_t> events;  // 4 per timed call
+    std::vector<hipEvent_t> events;  // per timed call: start, stop of beta, interface, sweep
+    std::vector<uint8_t> timed_empty;    // per timed call: bit k = phase k launched nothing
     size_t events_used = 0;
     // batch handles: K matrices sharing one table allocation
     bool is_batch = false;
@@ -241,26 +242,37 @@ int take_work(tds_plan* h, int64_t N, Work& w) {
 }
 
 // Theorem 2's interface values from the beta weights, in the plan's order
-hipError_t run_iface(tds_plan* h, const Work& w, double* xsep, int64_t N, hipStream_t s) {
+hipError_t run_iface(tds_plan* h, const Work& w, double* xsep, int64_t N, hipStream_t s,
+                     const KTime* tm = nullptr) {
     if (h->iface == TDS_IFACE_DICHOTOMY)
-        return launch_iface_dichotomy(h->dev, w.betaR, w.betaL, w.SR, w.SL, xsep, N, s);
+        return launch_iface_dichotomy(h->dev, w.betaR, w.betaL, w.SR, w.SL, xsep, N, s, tm);
     if (h->iface == TDS_IFACE_DENSE)
         return launch_iface_dense(h->dense_K, h->dense_Pc, h->dense_Mr, h->dev.P, w.betaR,
-                                  w.betaL, xsep, N, s);
-    return launch_iface(h->dev, w.betaR, w.betaL, xsep, N, s);
+                                  w.betaL, xsep, N, s, tm);
+    return launch_iface(h->dev, w.betaR, w.betaL, xsep, N, s, tm);
 }
 
-hipEvent_t* timing_slot(tds_plan* h) {
+constexpr size_t kTimedEvents = 6;   // start and stop of beta, interface, sweep
+
+// the start/stop pairs of one timed call (null when timing is off); the
+// events take the kernels' own start and end timestamps
+KTime* timing_slot(tds_plan* h) {
     if (!h->timing) return nullptr;
-    while (h->events.size() < h->events_used + 4) {
+    while (h->events.size() < h->events_used + kTimedEvents) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         h->events.push_back(e);
     }
-    hipEvent_t* ev = h->events.data() + h->events_used;
-    h->events_used += 4;
-    return ev;
+    static_assert(sizeof(KTime) == 2 * sizeof(hipEvent_t), "KTime is a pair of events");
+    KTime* tm = reinterpret_cast<KTime*>(h->events.data() + h->events_used);
+    h->events_used += kTimedEvents;
+    h->timed_empty.push_back(0);
+    return tm;
 }
+
+// phase k of the current timed call launches no kernel: its events stay
+// unrecorded and it reads as zero
+void empty_phase(tds_plan* h, int k) { h->timed_empty.back() |= (uint8_t)(1u << k); }
 
 int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hipStream_t s,
                 int sweep_mode) {
@@ -269,19 +281,23 @@ int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hi
     int rc = take_work(h, N, w);
     if (rc) return rc;
     double* xsep = w.xsep;
-    hipEvent_t* ev = timing_slot(h);
-    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TDS_EHIP;
-    if (t.P >= 2) {
-        if (launch_beta(t, F, mode != TDS_F64, N, w.betaR, w.betaL, s) != hipSuccess)
+    KTime* tm = timing_slot(h);
+    if (h->timing && !tm) return TDS_EHIP;
+    if (t.P >= 2 && N > 0) {
+        if (launch_beta(t, F, mode != TDS_F64, N, w.betaR, w.betaL, s, tm) != hipSuccess)
             return TDS_EHIP;
-        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TDS_EHIP;
-        if (run_iface(h, w, xsep, N, s) != hipSuccess) return TDS_EHIP;
-    } else if (ev && hipEventRecord(ev[1], s) != hipSuccess) {
-        return TDS_EHIP;
+        if (run_iface(h, w, xsep, N, s, tm ? tm + 1 : nullptr) != hipSuccess) return TDS_EHIP;
+    } else if (tm) {
+        empty_phase(h, 0);
+        empty_phase(h, 1);
     }
-    if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TDS_EHIP;
-    if (launch_sweep(t, F, X, N, sweep_mode, h->passes, xsep, s) != hipSuccess) return TDS_EHIP;
-    if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TDS_EHIP;
+    if (N > 0) {
+        if (launch_sweep(t, F, X, N, sweep_mode, h->passes, xsep, s, tm ? tm + 2 : nullptr) !=
+            hipSuccess)
+            return TDS_EHIP;
+    } else if (tm) {
+        empty_phase(h, 2);
+    }
     return TDS_OK;
 }
 
@@ -442,17 +458,26 @@ int tdsolve_timing_enable(tds_handle h, int32_t on) {
 int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls) {
     if (!h || !ms) return TDS_EINVAL;
     ms[0] = ms[1] = ms[2] = 0.0;
-    const size_t ncalls = h->events_used / 4;
-    if (ncalls > 0 && hipEventSynchronize(h->events[h->events_used - 1]) != hipSuccess)
-        return TDS_EHIP;
+    const size_t ncalls = h->events_used / kTimedEvents;
+    // wait for the last recorded stop event
+    for (size_t c = ncalls; c-- > 0;) {
+        int k = 2;
+        while (k >= 0 && ((h->timed_empty[c] >> k) & 1)) --k;
+        if (k < 0) continue;
+        if (hipEventSynchronize(h->events[kTimedEvents * c + 2 * k + 1]) != hipSuccess)
+            return TDS_EHIP;
+        break;
+    }
     for (size_t c = 0; c < ncalls; ++c) {
-        hipEvent_t* e = h->events.data() + 4 * c;
+        hipEvent_t* e = h->events.data() + kTimedEvents * c;
         for (int k = 0; k < 3; ++k) {
+            if ((h->timed_empty[c] >> k) & 1) continue;
             float v = 0.0f;
-            if (hipEventElapsedTime(&v, e[k], e[k + 1]) != hipSuccess) return TDS_EHIP;
+            if (hipEventElapsedTime(&v, e[2 * k], e[2 * k + 1]) != hipSuccess) return TDS_EHIP;
             ms[k] += v;
         }
     }
+    h->timed_empty.clear();
     if (calls) *calls = (int64_t)ncalls;
     h->events_used = 0;
     return TDS_OK;
@@ -655,12 +680,12 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
             return TDS_EHIP;
         h->desc = desc;
     }
-    hipEvent_t* ev = timing_slot(h);
-    if (ev && hipEventRecord(ev[0], (hipStream_t)stream) != hipSuccess) return TDS_EHIP;
-    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, ev,
+    KTime* tm = timing_slot(h);
+    if (h->timing && !tm) return TDS_EHIP;
+    if (tm && scans == 0) empty_phase(h, 1);
+    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, tm,
                      (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
-    if (ev && hipEventRecord(ev[3], (hipStream_t)stream) != hipSuccess) return TDS_EHIP;
     return TDS_OK;
 }
 

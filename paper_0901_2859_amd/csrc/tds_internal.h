@@ -84,25 +84,35 @@ constexpr int32_t kDenseMaxBlocks = 1024;
 int dense_interface_table(const HostTables& o, std::vector<double>& Kt, int32_t* Pc,
                           int32_t* Mr);
 
-// Kernel launchers (tdsolve_kernels.hip).  All return hipError_t.
+// Start and stop events of one kernel launch: with them, a launcher takes
+// the kernel's own start and end timestamps (phase timing).
+struct KTime {
+    hipEvent_t start;
+    hipEvent_t stop;
+};
+
+// Kernel launchers (tdsolve_kernels.hip).  All return hipError_t; `tm`
+// (may be null) times the launch.
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N,
-                       double* betaR, double* betaL, hipStream_t s);
+                       double* betaR, double* betaL, hipStream_t s,
+                       const KTime* tm = nullptr);
 hipError_t launch_iface(const DevTables& t, const double* betaR,
                         const double* betaL, double* xsep, int64_t N,
-                        hipStream_t s);
+                        hipStream_t s, const KTime* tm = nullptr);
 // the interface step by the dichotomy (Algorithm 4); SR, SL: work arrays
 // of (P + 1) x N doubles
 hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR,
                                   const double* betaL, double* SR, double* SL,
-                                  double* xsep, int64_t N, hipStream_t s);
+                                  double* xsep, int64_t N, hipStream_t s,
+                                  const KTime* tm = nullptr);
 // Theorem 2 as a dense product on the matrix cores (table from
 // dense_interface_table)
 hipError_t launch_iface_dense(const double* Kt, int32_t Pc, int32_t Mr, int32_t P,
                               const double* betaR, const double* betaL, double* xsep, int64_t N,
-                              hipStream_t s);
+                              hipStream_t s, const KTime* tm = nullptr);
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         int mode, int passes, const double* xsep,
-                        hipStream_t s);
+                        hipStream_t s, const KTime* tm = nullptr);
 
 // register-sweep row bucket (32, 64, 128) of a largest block size, 0 if the
 // streaming sweep is needed
@@ -131,11 +141,12 @@ struct BatchDesc {
 
 // The three steps for all matrices of a batch: one launch each.  `bucket`
 // is the common register-sweep row bucket (32 or 64).
-// `ev` (may be null): events [1] and [2] are recorded after the beta and
-// interface launches.
+// `tm` (may be null): start/stop events of the beta, interface and sweep
+// launches, in that order (the interface pair stays unrecorded when no
+// matrix has interface rows, scans == 0).
 hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items,
                         int64_t scans, int32_t bucket, int mode, int passes,
-                        hipEvent_t* ev, hipStream_t s);
+                        const KTime* tm, hipStream_t s);
 
 // uniform[-1, 1) values from a counter-based generator (timing inputs)
 hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipStream_t s);

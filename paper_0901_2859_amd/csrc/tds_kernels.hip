@@ -25,6 +25,8 @@
 // descriptor table.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "tdsolve.h"
 #include "tds_internal.h"
 
@@ -751,6 +753,17 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 
 // ==========================================================================
 // launchers
+
+// a kernel launch; with `tm`, its start and stop events take the kernel's
+// own start and end timestamps (phase timing without the dispatch gaps)
+template <typename Kern, typename... Args>
+static void launch_k(Kern kernel, dim3 g, dim3 b, uint32_t lds, hipStream_t s, const KTime* tm,
+                     Args... args) {
+    if (tm)
+        hipExtLaunchKernelGGL(kernel, g, b, lds, s, tm->start, tm->stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, g, b, lds, s, args...);
+}
 static inline dim3 grid2(int64_t N, int64_t y) {
     return dim3((unsigned)((N + kWG - 1) / kWG), (unsigned)y, 1);
 }
@@ -760,11 +773,11 @@ int32_t rows_bucket(int32_t max_rows) {
 }
 
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
-                       double* betaL, hipStream_t s) {
+                       double* betaL, hipStream_t s, const KTime* tm) {
     if (t.P < 2 || N == 0) return hipSuccess;
     const dim3 g((unsigned)((N + kBetaRhs - 1) / kBetaRhs), (unsigned)t.P, 1);
 #define TDS_BETA(TM, FT) \
-    hipLaunchKernelGGL((k_beta<TM, FT>), g, dim3(kWG), 0, s, t, (const FT*)F, N, betaR, betaL)
+    launch_k(k_beta<TM, FT>, g, dim3(kWG), 0, s, tm, t, (const FT*)F, N, betaR, betaL)
     switch (t.wpad_rows) {
         case 32:
             if (f32) TDS_BETA(32, float); else TDS_BETA(32, double);
@@ -792,44 +805,44 @@ void scan_shape(int32_t P, int32_t max_groups, int32_t* per, int32_t* G) {
 }
 
 hipError_t launch_iface(const DevTables& t, const double* betaR, const double* betaL,
-                        double* xsep, int64_t N, hipStream_t s) {
+                        double* xsep, int64_t N, hipStream_t s, const KTime* tm) {
     if (t.P < 2 || N == 0) return hipSuccess;
     int32_t per, G;
     scan_shape(t.P, kScanMaxGroupsSingle, &per, &G);
     const size_t lds = sizeof(double) * scan_lds_doubles(G, per);
-    hipLaunchKernelGGL(k_iface, dim3((unsigned)((N + kScanRhs - 1) / kScanRhs)),
-                       dim3(kScanRhs * G), lds, s, t, N, per, G, betaR, betaL, xsep);
+    launch_k(k_iface, dim3((unsigned)((N + kScanRhs - 1) / kScanRhs)),
+                       dim3(kScanRhs * G), lds, s, tm, t, N, per, G, betaR, betaL, xsep);
     return hipGetLastError();
 }
 
 hipError_t launch_iface_dense(const double* Kt, int32_t Pc, int32_t Mr, int32_t P,
                               const double* betaR, const double* betaL, double* xsep, int64_t N,
-                              hipStream_t s) {
+                              hipStream_t s, const KTime* tm) {
     if (P < 2 || N == 0) return hipSuccess;
     if (Pc % 4 != 0 || Pc < P || Mr % kDenseRows != 0 || Mr < P - 1) return hipErrorInvalidValue;
     const dim3 g((unsigned)((N + kDenseCols - 1) / kDenseCols),
                  (unsigned)((P - 1 + kDenseRows - 1) / kDenseRows), 1);
-    hipLaunchKernelGGL(k_iface_dense, g, dim3(kWG), 0, s, Kt, Pc, Mr, P, N, betaR, betaL, xsep);
+    launch_k(k_iface_dense, g, dim3(kWG), 0, s, tm, Kt, Pc, Mr, P, N, betaR, betaL, xsep);
     return hipGetLastError();
 }
 
 hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR, const double* betaL,
                                   double* SR, double* SL, double* xsep, int64_t N,
-                                  hipStream_t s) {
+                                  hipStream_t s, const KTime* tm) {
     if (t.P < 2 || N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_iface_dich, dim3((unsigned)((N + kDichRhs - 1) / kDichRhs)), dim3(kWG),
-                       0, s, t, N, betaR, betaL, SR, SL, xsep);
+    launch_k(k_iface_dich, dim3((unsigned)((N + kDichRhs - 1) / kDichRhs)), dim3(kWG), 0, s, tm,
+             t, N, betaR, betaL, SR, SL, xsep);
     return hipGetLastError();
 }
 
 template <typename Fin, typename Xout, int KIND, bool GEN>
 static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, int passes,
-                       const double* xsep, hipStream_t s) {
+                       const double* xsep, hipStream_t s, const KTime* tm) {
     const int m = t.max_rows;
     const dim3 g = grid2(N, t.P);
-#define TDS_SWEEP(TM)                                                                        \
-    hipLaunchKernelGGL((k_sweep_reg<TM, Fin, Xout, KIND, GEN>), g, dim3(kWG), 0, s, t,       \
-                       (const Fin*)F, (Xout*)X, N, xsep, passes)
+#define TDS_SWEEP(TM)                                                                   \
+    launch_k(k_sweep_reg<TM, Fin, Xout, KIND, GEN>, g, dim3(kWG), 0, s, tm, t, (const Fin*)F, \
+             (Xout*)X, N, xsep, passes)
     if (m <= 16)
         TDS_SWEEP(16);
     else if (m <= 32)
@@ -839,30 +852,29 @@ static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, in
     else if (m <= kRegMaxRows && KIND != kSweepRefined)
         TDS_SWEEP(128);
     else
-        hipLaunchKernelGGL(
-            (k_sweep_stream<Fin, Xout, KIND == kSweep32 ? kSweep32 : kSweep64, GEN>), g,
-            dim3(kWG), 0, s, t, (const Fin*)F, (Xout*)X, N, xsep);
+        launch_k(k_sweep_stream<Fin, Xout, KIND == kSweep32 ? kSweep32 : kSweep64, GEN>, g,
+                 dim3(kWG), 0, s, tm, t, (const Fin*)F, (Xout*)X, N, xsep);
 #undef TDS_SWEEP
 }
 
 template <typename Fin, typename Xout, int KIND>
 static void go_sweep(const DevTables& t, const void* F, void* X, int64_t N, int passes,
-                     const double* xsep, hipStream_t s) {
+                     const double* xsep, hipStream_t s, const KTime* tm) {
     if (t.general)
-        go_sweep_t<Fin, Xout, KIND, true>(t, F, X, N, passes, xsep, s);
+        go_sweep_t<Fin, Xout, KIND, true>(t, F, X, N, passes, xsep, s, tm);
     else
-        go_sweep_t<Fin, Xout, KIND, false>(t, F, X, N, passes, xsep, s);
+        go_sweep_t<Fin, Xout, KIND, false>(t, F, X, N, passes, xsep, s, tm);
 }
 
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, int mode,
-                        int passes, const double* xsep, hipStream_t s) {
+                        int passes, const double* xsep, hipStream_t s, const KTime* tm) {
     if (N == 0) return hipSuccess;
     switch (mode) {
-        case TDS_F64: go_sweep<double, double, kSweep64>(t, F, X, N, passes, xsep, s); break;
-        case TDS_F32_WIDE: go_sweep<float, double, kSweep64>(t, F, X, N, passes, xsep, s); break;
-        case TDS_F32: go_sweep<float, float, kSweep32>(t, F, X, N, passes, xsep, s); break;
+        case TDS_F64: go_sweep<double, double, kSweep64>(t, F, X, N, passes, xsep, s, tm); break;
+        case TDS_F32_WIDE: go_sweep<float, double, kSweep64>(t, F, X, N, passes, xsep, s, tm); break;
+        case TDS_F32: go_sweep<float, float, kSweep32>(t, F, X, N, passes, xsep, s, tm); break;
         case TDS_F32_REFINED:
-            go_sweep<float, double, kSweepRefined>(t, F, X, N, passes, xsep, s);
+            go_sweep<float, double, kSweepRefined>(t, F, X, N, passes, xsep, s, tm);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -871,30 +883,29 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
 
 template <int TM>
 static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, int passes,
-                        hipStream_t s) {
+                        hipStream_t s, const KTime* tm) {
     const dim3 g((unsigned)items);
     switch (mode) {
         case TDS_F64:
-            hipLaunchKernelGGL((k_sweep_batch<TM, double, double, kSweep64>), g, dim3(kWG), 0, s,
-                               D, K, passes);
+            launch_k(k_sweep_batch<TM, double, double, kSweep64>, g, dim3(kWG), 0, s, tm,
+                     D, K, passes);
             break;
         case TDS_F32_WIDE:
-            hipLaunchKernelGGL((k_sweep_batch<TM, float, double, kSweep64>), g, dim3(kWG), 0, s,
-                               D, K, passes);
+            launch_k(k_sweep_batch<TM, float, double, kSweep64>, g, dim3(kWG), 0, s, tm,
+                     D, K, passes);
             break;
         case TDS_F32:
-            hipLaunchKernelGGL((k_sweep_batch<TM, float, float, kSweep32>), g, dim3(kWG), 0, s,
-                               D, K, passes);
+            launch_k(k_sweep_batch<TM, float, float, kSweep32>, g, dim3(kWG), 0, s, tm,
+                     D, K, passes);
             break;
         default:
-            hipLaunchKernelGGL((k_sweep_batch<TM, float, double, kSweepRefined>), g, dim3(kWG), 0,
-                               s, D, K, passes);
+            launch_k(k_sweep_batch<TM, float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D, K, passes);
             break;
     }
 }
 
 hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t scans,
-                        int32_t bucket, int mode, int passes, hipEvent_t* ev, hipStream_t s) {
+                        int32_t bucket, int mode, int passes, const KTime* tm, hipStream_t s) {
     if (items == 0) return hipSuccess;
     if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
     if (items > INT32_MAX / kBetaWaves) return hipErrorInvalidValue;
@@ -902,29 +913,27 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
     const bool f64in = (mode == TDS_F64);
     if (bucket == 32) {
         if (f64in)
-            hipLaunchKernelGGL((k_beta_batch<32, double>), g, dim3(kWG), 0, s, D, K);
+            launch_k(k_beta_batch<32, double>, g, dim3(kWG), 0, s, tm, D, K);
         else
-            hipLaunchKernelGGL((k_beta_batch<32, float>), g, dim3(kWG), 0, s, D, K);
+            launch_k(k_beta_batch<32, float>, g, dim3(kWG), 0, s, tm, D, K);
     } else {
         if (f64in)
-            hipLaunchKernelGGL((k_beta_batch<64, double>), g, dim3(kWG), 0, s, D, K);
+            launch_k(k_beta_batch<64, double>, g, dim3(kWG), 0, s, tm, D, K);
         else
-            hipLaunchKernelGGL((k_beta_batch<64, float>), g, dim3(kWG), 0, s, D, K);
+            launch_k(k_beta_batch<64, float>, g, dim3(kWG), 0, s, tm, D, K);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (scans > 0) {
-        hipLaunchKernelGGL(k_iface_batch, dim3((unsigned)scans), dim3(kScanRhs * kScanMaxGroups),
-                           0, s, D, K);
+        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanRhs * kScanMaxGroups), 0, s,
+                 tm ? tm + 1 : nullptr, D, K);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     if (bucket == 32)
-        batch_sweep<32>(D, K, items, mode, passes, s);
+        batch_sweep<32>(D, K, items, mode, passes, s, tm ? tm + 2 : nullptr);
     else
-        batch_sweep<64>(D, K, items, mode, passes, s);
+        batch_sweep<64>(D, K, items, mode, passes, s, tm ? tm + 2 : nullptr);
     return hipGetLastError();
 }
 
