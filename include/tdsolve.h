@@ -208,6 +208,17 @@ int tdsolve_prepare_host_general(const double* lower, const double* diag,
                                  int64_t* starts, double* wR, double* wL,
                                  double* rho, double* lam, double* diag_inv);
 
+/* Host-only copy of the coefficients of TDS_IFACE_DENSE (Theorem 2,
+ * eq. theor_2, as one matrix), for checks without a GPU.  K receives
+ * (P-1) x 2P doubles, row-major: for the interface row k = 1..P-1, row k-1
+ * holds at column j < k the ratio product Z^R(s_{j+1}, s_k) =
+ * rho_{j+1} ... rho_{k-1} (the weight of beta^R_j) and at column P + j,
+ * j >= k, Z^L(s_j, s_k) = lam_k ... lam_{j-1} (the weight of beta^L_j);
+ * every other entry is 0.  2 <= P <= 1024 (else TDS_EINVAL /
+ * TDS_EUNSUPPORTED); other errors as tdsolve_prepare_host. */
+int tdsolve_dense_table_host(const double* a, const double* b, int64_t M,
+                             int32_t P, double* K);
+
 /* Block count the library would choose for P == 0. */
 int32_t tdsolve_default_blocks(int64_t M);
 

@@ -558,6 +558,26 @@ int tdsolve_prepare_host_general(const double* lower, const double* diag, const 
     return TDS_OK;
 }
 
+int tdsolve_dense_table_host(const double* a, const double* b, int64_t M, int32_t P, double* K) {
+    if (!K || P < 2) return TDS_EINVAL;
+    if (P > kDenseMaxBlocks) return TDS_EUNSUPPORTED;
+    HostTables o;
+    int rc = host_prepare(a, b, M, P, o);
+    if (rc) return rc;
+    std::vector<double> Kt;
+    int32_t pc = 0, mr = 0;
+    rc = dense_interface_table(o, Kt, &pc, &mr);
+    if (rc) return rc;
+    // device layout Kt[kk][r] (kk = j or Pc + j) -> K[r][j] / K[r][P + j]
+    const size_t w = 2 * (size_t)P;
+    for (int32_t r = 0; r < P - 1; ++r)
+        for (int32_t j = 0; j < P; ++j) {
+            K[(size_t)r * w + j] = Kt[(size_t)j * mr + r];
+            K[(size_t)r * w + P + j] = Kt[((size_t)pc + j) * mr + r];
+        }
+    return TDS_OK;
+}
+
 int32_t tdsolve_default_blocks(int64_t M) { return default_blocks(M); }
 
 int tdsolve_destroy(tds_handle h) {

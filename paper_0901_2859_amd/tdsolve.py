@@ -32,7 +32,7 @@ SYMBOLS = [
     "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
-    "tdsolve_prepare_host_general", "tdsolve_set_interface",
+    "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
 ]
 
 _lib = None
@@ -72,6 +72,7 @@ def lib():
     L.tdsolve_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.tdsolve_prepare_host.argtypes = [dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
     L.tdsolve_prepare_host_general.argtypes = [dp, dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
+    L.tdsolve_dense_table_host.argtypes = [dp, dp, i64, i32, dp]
     L.tdsolve_default_blocks.argtypes = [i64]
     L.tdsolve_default_blocks.restype = i32
     L.tdsolve_destroy.argtypes = [vp]
@@ -129,6 +130,18 @@ def prepare_host(a, b, P: int):
     _check(L.tdsolve_prepare_host(_ptr(a), _ptr(b), M, P, _ptr(starts), _ptr(wR), _ptr(wL),
                                   _ptr(rho), _ptr(lam), _ptr(dinv)), "tdsolve_prepare_host")
     return dict(starts=starts, wR=wR, wL=wL, rho=rho, lam=lam, diag_inv=dinv, P=P, M=M)
+
+
+def dense_table_host(a, b, P: int):
+    """Theorem 2's coefficients as the (P-1) x 2P matrix of the dense
+    interface order (tdsolve_dense_table_host), computed on the host."""
+    L = lib()
+    b = _host_f64(b)
+    M = b.shape[0]
+    a = _host_f64(a) if M > 1 else np.zeros(1)
+    K = np.zeros((max(P - 1, 0), 2 * P))
+    _check(L.tdsolve_dense_table_host(_ptr(a), _ptr(b), M, P, _ptr(K)), "tdsolve_dense_table_host")
+    return K
 
 
 def prepare_host_general(lower, diag, upper, P: int):

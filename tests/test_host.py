@@ -247,3 +247,40 @@ def test_new_entry_points_reject_bad_arguments_without_gpu():
     assert L.tdsolve_set_interface(None, 1) == -1
     assert L.tdsolve_prepare_host_general(P_(a), P_(b), None, 10, 2, None, None, None, None,
                                           None, None) == -1
+
+
+@pytest.mark.parametrize("M,P", [(64, 8), (300, 10), (1000, 37), (4096, 64), (2000, 130)])
+def test_dense_table_host_is_theorem2_ratio_products(M, P):
+    # the coefficient matrix of the dense interface order, entry by entry
+    # against the oracle's Z vectors at the interface rows, and its product
+    # with the oracle's betas against the oracle's literal double sum
+    w = wl.random_dominant(seed=M + P, M=M, N=5)
+    a, b, F = w["a"], w["b"], w["F"]
+    prep = method.prepare(a, b, P)
+    s, ZR, ZL = prep["s"], prep["ZR"], prep["ZL"]
+    K = t.dense_table_host(a, b, P)
+    assert K.shape == (P - 1, 2 * P)
+    Kor = np.zeros((P - 1, 2 * P))
+    for k in range(1, P):
+        sk = int(s[k])
+        for j in range(k):
+            Kor[k - 1, j] = ZR[int(s[j + 1])][sk]
+        for j in range(k, P):
+            Kor[k - 1, P + j] = ZL[int(s[j])][sk]
+    np.testing.assert_allclose(K, Kor, rtol=1e-11, atol=1e-300)
+    bR, bL = method.betas(prep, F)
+    xs = method.interface_theor2(prep, bR, bL)
+    X = K[:, :P] @ bR + K[:, P:] @ bL
+    assert np.max(np.abs(X - xs)) <= 1e-12 * np.max(np.abs(xs))
+
+
+def test_dense_table_host_limits():
+    a, b = -np.ones(2099), 3 * np.ones(2100)
+    with pytest.raises(t.TdsError) as err:
+        t.dense_table_host(a, b, 1)
+    assert err.value.code == -1                 # TDS_EINVAL: no interface rows
+    with pytest.raises(t.TdsError) as err:
+        t.dense_table_host(a, b, 1025)
+    assert err.value.code == -6                 # TDS_EUNSUPPORTED: P > 1024
+    K = t.dense_table_host(a[:3], b[:4], 2)     # one interface row: both parts 1 at j = 0, 1
+    assert np.array_equal(K, np.array([[1.0, 0.0, 0.0, 1.0]]))
