@@ -120,7 +120,8 @@ int tdsolve_prepare_general(const double* lower, const double* diag,
 /* Solve the series (Algorithm 1 with Algorithm 3 step 2 for the interface
  * rows).  F: device [M][N] (double for TDS_F64, float otherwise).
  * X: device [M][N] (float for TDS_F32, double otherwise).  N >= 0 (N == 0
- * is a no-op).  Asynchronous on `stream`. */
+ * is a no-op; TDS_EUNSUPPORTED when N / 16 exceeds the launch grid,
+ * 2^31 - 1).  Asynchronous on `stream`. */
 int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N,
                    int32_t mode, void* stream);
 

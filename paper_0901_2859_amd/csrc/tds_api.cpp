@@ -209,7 +209,8 @@ size_t x_elem(int32_t m) { return m == TDS_F32 ? 4 : 8; }
 int check_common(tds_plan* h, int64_t N, int32_t mode) {
     if (!h || h->is_batch) return TDS_EINVAL;
     if (N < 0 || !valid_mode(mode)) return TDS_EINVAL;
-    if ((N + kWG - 1) / kWG > 0x7fffffffLL) return TDS_EUNSUPPORTED;
+    // the narrowest workgroups take 16 right-hand sides (interface steps)
+    if ((N + kScanRhs - 1) / kScanRhs > 0x7fffffffLL) return TDS_EUNSUPPORTED;
     return TDS_OK;
 }
 
