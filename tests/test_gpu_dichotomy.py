@@ -78,3 +78,23 @@ def test_set_interface_rejects_unknown_order():
     plan = t.Plan(a, b, 4)
     with pytest.raises(t.TdsError):
         t._check(t.lib().tdsolve_set_interface(plan._h, 7), "tdsolve_set_interface")
+
+
+def test_dichotomy_general_matrix_matches_oracle():
+    # non-symmetric A: the dichotomy's products of transfer factors carry the
+    # similarity's ratios as the recurrences do
+    rng = np.random.default_rng(8)
+    M, N, P = 1200, 40, 20
+    up = rng.uniform(0.2, 1.0, size=M - 1) * rng.choice([-1.0, 1.0], size=M - 1)
+    lo = np.sign(up) * rng.uniform(0.2, 1.0, size=M - 1)
+    d = (np.concatenate([[0], np.abs(lo)]) + np.concatenate([np.abs(up), [0]]) + 0.3) * \
+        rng.choice([-1.0, 1.0], size=M)
+    F = rng.uniform(-1, 1, size=(M, N))
+    low, upp = np.concatenate([[0.0], lo]), np.concatenate([up, [0.0]])
+    ref = np.stack([oracle.tridiag_general(low, d, upp, F[:, n]) for n in range(N)], 1)
+    plan = t.Plan.general(lo, d, up, P)
+    Fd = torch.from_numpy(F).to(DEV)
+    plan.set_interface("dichotomy")
+    X = plan.solve(Fd, mode="f64").cpu().numpy()
+    scale = np.max(np.abs(ref), axis=0)
+    assert np.max(np.abs(X - ref).max(axis=0) / scale) <= 1e-11
