@@ -658,7 +658,8 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         d.T = t;
         d.item0 = items;
         d.scan0 = scans;
-        scan_shape(t.P, kScanBatchGroups, &d.per, &d.G);
+        batch_scan_shape(t.P, &d.per, &d.G, &d.lgR);
+        d.pad_ = 0;
         const size_t nb = align256(sizeof(double) * (size_t)t.P * (size_t)n);
         d.betaR = (double*)bytes;
         d.betaL = (double*)(bytes + nb);
@@ -666,7 +667,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         bytes += 2 * nb + align256(sizeof(double) * (size_t)(t.P > 1 ? t.P - 1 : 1) * (size_t)n);
         if (n > 0) {
             items += (int64_t)t.P * ((n + kWG - 1) / kWG);
-            if (t.P > 1) scans += (n + kScanRhs - 1) / kScanRhs;
+            if (t.P > 1) scans += (n + ((int64_t)1 << d.lgR) - 1) >> d.lgR;
         }
     }
     if (items == 0) return TDS_OK;

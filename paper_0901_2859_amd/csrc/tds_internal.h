@@ -12,8 +12,10 @@ namespace tds {
 // Workgroup size of every per-block kernel: 4 wavefronts of 64 lanes, each
 // lane one right-hand side.
 constexpr int kWG = 256;
-constexpr int kScanRhs = 16;      // right-hand sides per interface-scan workgroup
-constexpr int kScanBatchGroups = 16;   // scan groups per batch workgroup
+constexpr int kScanRhs = 16;      // right-hand sides per scan group (single-matrix kernel)
+constexpr int kScanRhsLog2 = 4;
+constexpr int kScanBatchThreads = 256;   // batch scan workgroup: G groups x R RHS
+constexpr int kScanBatchMaxGroups = 32;  // groups per batch scan workgroup, at most
 
 // Largest block (rows of one segment) handled by the register-resident
 // sweep; larger blocks take the streaming sweep, which keeps the forward
@@ -120,11 +122,15 @@ int32_t rows_bucket(int32_t max_rows);
 // shape of the two-level interface scan: blocks per group, groups
 // (<= max_groups; 16 for the batch kernels)
 void scan_shape(int32_t P, int32_t max_groups, int32_t* per, int32_t* G);
+// the batch kernel's shape for one matrix: per, G and log2 R with
+// G R <= kScanBatchThreads
+void batch_scan_shape(int32_t P, int32_t* per, int32_t* G, int32_t* lgR);
 
 // One matrix of a batch: its tables, its series and its slices of the work
 // buffer, and where its work items start in the batch launches (item0: beta
 // and sweep items, P * ceil(N/256) of them; scan0: interface workgroups,
-// ceil(N/64) of them).
+// ceil(N / 2^lgR) of them, each G groups of `per` blocks x 2^lgR right-hand
+// sides, from batch_scan_shape).
 struct BatchDesc {
     const void* F;
     void* X;
@@ -137,6 +143,8 @@ struct BatchDesc {
     int64_t scan0;
     int32_t per;
     int32_t G;
+    int32_t lgR;
+    int32_t pad_;
 };
 
 // The three steps for all matrices of a batch: one launch each.  `bucket`

@@ -148,6 +148,54 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
     }
 }
 
+// Batch beta weights: one workgroup per item (block j x 256 right-hand
+// sides), each wavefront 64 right-hand sides and every row of the block.
+// The batch's blocks are short (<= TMAX = 32 or 64 rows), so beta_item's
+// split of the rows over the four wavefronts would leave a workgroup about
+// 8 KB of input; here a workgroup carries four times that, with a quarter
+// of the launches and no LDS reduction.  Each wavefront forms the four
+// quarter sums of beta_item separately and adds them in the order of its
+// reduction, so the weights are bitwise those of a single-matrix plan.
+template <int TMAX, typename Fin>
+__device__ __forceinline__ void beta_rows_item(const DevTables& T, const Fin* __restrict__ F,
+                                               int64_t N, int32_t j, int64_t n0,
+                                               double* __restrict__ betaR,
+                                               double* __restrict__ betaL) {
+    if (n0 >= N) return;                                  // uniform per wavefront
+    const int64_t lo = cst(T.starts)[j];
+    const int t = (int)(cst(T.starts)[j + 1] - lo);
+    const int lane = threadIdx.x % kBetaRhs;
+    const bool live = n0 + lane < N;
+    const uint32_t off = (uint32_t)(live ? lane : N - 1 - n0) * sizeof(Fin);
+    const Fin* fb = F + lo * N + n0;
+    constexpr int TQ = TMAX / kBetaWaves;
+    const cptr<double2> w = cst(T.wpad + (int64_t)j * TMAX);
+    Fin v[TMAX];
+#pragma unroll
+    for (int r = 0; r < TMAX; ++r) v[r] = at_off(fb + (int64_t)(r < t ? r : t - 1) * N, off);
+    double bR = 0.0, bL = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBetaWaves; ++q) {
+        double qR = 0.0, qL = 0.0;
+#pragma unroll
+        for (int r = 0; r < TQ; ++r) {
+            const double cR = w[q * TQ + r].x, cL = w[q * TQ + r].y;
+            qR = fma(cR, (double)v[q * TQ + r], qR);
+            qL = fma(cL, (double)v[q * TQ + r], qL);
+        }
+        if (q == 0) {
+            bR = qR;
+            bL = qL;
+        } else {
+            bR += qR;
+            bL += qL;
+        }
+    }
+    if (!live) return;
+    if (j < T.P - 1) betaR[(int64_t)j * N + n0 + lane] = bR;
+    if (j > 0) betaL[(int64_t)j * N + n0 + lane] = bL;
+}
+
 // ==========================================================================
 // Interface step (Theorem 2): the O(P) recurrences
 //   forward   y_j = rho_j y_{j-1} + beta^R_j,  j = 0..P-2 (y_{-1} = 0),
@@ -155,18 +203,20 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
 //   backward  z_j = lam_j z_{j+1} + beta^L_j,  j = P-1..1 (z_P = 0),
 //             so that S^L_j = z_j;
 //   x(s_k) = S^R_k + S^L_k, k = 1..P-1  (xsep row k-1),
-// as a two-level scan: workgroup = 16 right-hand sides x up to 16 groups of
-// `per` consecutive blocks (a wavefront covers 4 groups; each group's row
-// access is one 128-byte line).  Each thread loads its group's beta values
-// once, scans them with zero input, the group carries (product of the
-// factors, partial value) are combined through LDS, then each thread
-// finishes its group with the true input.  When a thread keeps its beta
-// values in registers (per <= 8), S^R goes to LDS and the thread owning the
-// same interface row in the backward direction writes S^R + S^L to xsep
-// once; otherwise S^R is written to xsep and S^L added after a barrier.
-constexpr int kScanMaxGroups = kScanBatchGroups;   // batch workgroups (one shape for all)
+// as a two-level scan: workgroup = R right-hand sides x G groups of `per`
+// consecutive blocks (single-matrix kernel: R = 16, up to 64 groups; batch
+// kernel: G x R = 256 with a shape per matrix, see batch_scan_shape).  Each
+// thread loads its group's beta values once, scans them with zero input,
+// the group carries (product of the factors, partial value) are combined
+// through LDS, then each thread finishes its group with the true input.
+// When a thread keeps its beta values in registers (per <= MAXPER: 8 in the
+// single-matrix kernel, 16 in the batch kernel), S^R goes to LDS and the
+// thread owning the same interface row in the backward direction writes
+// S^R + S^L to xsep once; otherwise S^R is written to xsep and S^L added
+// after a barrier.
 constexpr int kScanMaxGroupsSingle = 64;  // single-matrix workgroups (up to 1024 threads)
-constexpr int kScanMaxPer = 8;     // beta values a thread keeps in registers
+constexpr int kScanMaxPer = 8;     // beta values a thread keeps in registers (single)
+constexpr int kScanMaxPerBatch = 16;       // the same in the batch kernel
 constexpr int kChainChunk = 8;     // beta values read per memory round trip
 
 // S^R recurrence y <- rho_j y + beta^R_j for j = j0 .. j1-1 (rho_0 is not
@@ -219,20 +269,24 @@ __device__ __forceinline__ double chain_left(double z, const cptr<double> lam, i
 // LDS of one interface-scan workgroup (G groups): the group carries
 // carry[2][G][kScanRhs], the products of the factors prod[2][G] and, when
 // the beta values stay in registers, S^R by interface row sr[G per][kScanRhs].
-__host__ __device__ constexpr size_t scan_lds_doubles(int32_t G, int32_t per) {
-    return (size_t)2 * G * kScanRhs + 2 * G +
-           (per <= kScanMaxPer ? (size_t)G * per * kScanRhs : 0);
+__host__ __device__ constexpr size_t scan_lds_doubles(int32_t G, int32_t per,
+                                                      int32_t maxper = kScanMaxPer,
+                                                      int32_t R = kScanRhs) {
+    return (size_t)2 * G * R + 2 * G + (per <= maxper ? (size_t)G * per * R : 0);
 }
 
+template <int MAXPER>
 __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_t per,
                                            int32_t G, const double* __restrict__ betaR,
                                            const double* __restrict__ betaL,
                                            double* __restrict__ xsep, int64_t sblk,
-                                           double* smem) {
+                                           double* smem, int lgR) {
     const int32_t P = T.P;
-    const int lane = threadIdx.x % kScanRhs;
-    const int g = threadIdx.x / kScanRhs;
-    const int64_t n = sblk * kScanRhs + lane;
+    // R = 2^lgR right-hand sides per group, one lane each
+    const int R = 1 << lgR;
+    const int lane = threadIdx.x & (R - 1);
+    const int g = threadIdx.x >> lgR;
+    const int64_t n = (sblk << lgR) + lane;
     const bool grp = g < G;                 // this thread's group exists
     const bool live = (n < N) && grp;
     const cptr<double> rho = cst(T.rho), lam = cst(T.lam);
@@ -241,8 +295,8 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
     const int32_t b1 = P - 1 - g * per, b0 = max(b1 - per, 0);
 
     double yl = 0.0, pr = 1.0, zl = 0.0, pl = 1.0;
-    double bRv[kScanMaxPer], bLv[kScanMaxPer];
-    const bool keep = per <= kScanMaxPer;
+    double bRv[MAXPER], bLv[MAXPER];
+    const bool keep = per <= MAXPER;
     if (grp) {
         // the products of the factors do not depend on the right-hand side
         for (int32_t j = f0; j < f1; ++j) pr *= (j > 0) ? rho[j] : 0.0;
@@ -251,13 +305,13 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
     if (live) {
         if (keep) {
 #pragma unroll
-            for (int u = 0; u < kScanMaxPer; ++u) {
+            for (int u = 0; u < MAXPER; ++u) {
                 const int32_t jf = f0 + u, jb = b1 - u;
                 bRv[u] = (jf < f1) ? betaR[(int64_t)jf * N + n] : 0.0;
                 bLv[u] = (jb > b0) ? betaL[(int64_t)jb * N + n] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < kScanMaxPer; ++u) {
+            for (int u = 0; u < MAXPER; ++u) {
                 const int32_t jf = f0 + u, jb = b1 - u;
                 if (jf < f1) yl = fma((jf > 0) ? rho[jf] : 0.0, yl, bRv[u]);
                 if (jb > b0) zl = fma((jb < P - 1) ? lam[jb] : 0.0, zl, bLv[u]);
@@ -267,12 +321,12 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             zl = chain_left(zl, lam, P, betaL, N, n, b1, b0, nullptr);
         }
     }
-    double* carry = smem;                              // [2][G][kScanRhs]
-    double* prod = smem + 2 * G * kScanRhs;            // [2][G]
-    double* sr = prod + 2 * G;                          // [G per][kScanRhs]
+    double* carry = smem;                              // [2][G][R]
+    double* prod = smem + 2 * G * R;            // [2][G]
+    double* sr = prod + 2 * G;                          // [G per][R]
     if (grp) {
-        carry[g * kScanRhs + lane] = yl;
-        carry[(G + g) * kScanRhs + lane] = zl;
+        carry[g * R + lane] = yl;
+        carry[(G + g) * R + lane] = zl;
         if (lane == 0) {
             prod[g] = pr;
             prod[G + g] = pl;
@@ -281,19 +335,19 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
     __syncthreads();
     double yin = 0.0, zin = 0.0;
     for (int q = 0; q < g && q < G; ++q) {
-        yin = fma(prod[q], yin, carry[q * kScanRhs + lane]);
-        zin = fma(prod[G + q], zin, carry[(G + q) * kScanRhs + lane]);
+        yin = fma(prod[q], yin, carry[q * R + lane]);
+        zin = fma(prod[G + q], zin, carry[(G + q) * R + lane]);
     }
     // finish the forward group: y_j = S^R_{j+1} into LDS or xsep
     if (live) {
         double y = yin;
         if (keep) {
 #pragma unroll
-            for (int u = 0; u < kScanMaxPer; ++u) {
+            for (int u = 0; u < MAXPER; ++u) {
                 const int32_t j = f0 + u;
                 if (j < f1) {
                     y = fma((j > 0) ? rho[j] : 0.0, y, bRv[u]);
-                    sr[j * kScanRhs + lane] = y;
+                    sr[j * R + lane] = y;
                 }
             }
         } else {
@@ -305,11 +359,11 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
     double z = zin;
     if (keep) {
 #pragma unroll
-        for (int u = 0; u < kScanMaxPer; ++u) {
+        for (int u = 0; u < MAXPER; ++u) {
             const int32_t j = b1 - u;
             if (j > b0) {
                 z = fma((j < P - 1) ? lam[j] : 0.0, z, bLv[u]);
-                xsep[(int64_t)(j - 1) * N + n] = sr[(j - 1) * kScanRhs + lane] + z;   // S^R_j + S^L_j
+                xsep[(int64_t)(j - 1) * N + n] = sr[(j - 1) * R + lane] + z;   // S^R_j + S^L_j
             }
         }
     } else {
@@ -678,7 +732,8 @@ __global__ __launch_bounds__(kScanRhs * kScanMaxGroupsSingle) void k_iface(
     DevTables T, int64_t N, int32_t per, int32_t G, const double* __restrict__ betaR,
     const double* __restrict__ betaL, double* __restrict__ xsep) {
     extern __shared__ double scan_smem[];
-    iface_item(T, N, per, G, betaR, betaL, xsep, (int64_t)blockIdx.x, scan_smem);
+    iface_item<kScanMaxPer>(T, N, per, G, betaR, betaL, xsep, (int64_t)blockIdx.x, scan_smem,
+                            kScanRhsLog2);
 }
 
 template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
@@ -720,31 +775,36 @@ __device__ __forceinline__ int32_t find_desc(const BatchDesc* __restrict__ D, in
     return lo;
 }
 
-// the beta launch has kBetaWaves workgroups per item (one per 64-RHS
-// quarter of the item's 256 right-hand sides)
+// one workgroup per item: wavefront wv takes right-hand sides wv*64 .. +63
+// of the item's 256 (beta_rows_item)
 template <int TMAX, typename Fin>
 __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict__ D, int32_t K) {
-    __shared__ double2 red[(kBetaWaves - 1) * kBetaRhs];
-    const int64_t item = blockIdx.x / kBetaWaves;
-    const int32_t sub = blockIdx.x % kBetaWaves;
+    const int64_t item = blockIdx.x;
     const int32_t k = find_desc(D, K, item, false);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
     if (d.T.P < 2 || local >= (int64_t)d.T.P * tiles) return;
-    beta_item<TMAX, Fin>(d.T, (const Fin*)d.F, d.N, (int32_t)(local / tiles),
-                         (local % tiles) * kBetaWaves + sub, d.betaR, d.betaL, red);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kBetaRhs);
+    beta_rows_item<TMAX, Fin>(d.T, (const Fin*)d.F, d.N, (int32_t)(local / tiles),
+                              (local % tiles) * kWG + wv * kBetaRhs, d.betaR, d.betaL);
 }
 
-__global__ __launch_bounds__(kScanRhs * kScanMaxGroups) void k_iface_batch(
+// one workgroup of kScanBatchThreads per R_k right-hand sides of matrix k
+// (G_k R_k <= kScanBatchThreads); LDS for the largest shape, G R = 256 with
+// per <= kScanMaxPerBatch
+__global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
     const BatchDesc* __restrict__ D, int32_t K) {
-    __shared__ double S[scan_lds_doubles(kScanMaxGroups, kScanMaxPer)];
+    // carries 2 G R + factors 2 G + S^R by row G per R, with G R <= 256
+    __shared__ double S[2 * kScanBatchThreads + 2 * kScanBatchMaxGroups +
+                        kScanBatchThreads * kScanMaxPerBatch];
     const int64_t item = blockIdx.x;
     const int32_t k = find_desc(D, K, item, true);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.scan0;
-    if (d.T.P < 2 || local * kScanRhs >= d.N) return;   // uniform per workgroup
-    iface_item(d.T, d.N, d.per, d.G, d.betaR, d.betaL, d.xsep, local, S);
+    if (d.T.P < 2 || (local << d.lgR) >= d.N) return;   // uniform per workgroup
+    iface_item<kScanMaxPerBatch>(d.T, d.N, d.per, d.G, d.betaR, d.betaL, d.xsep, local, S,
+                                 d.lgR);
 }
 
 template <int TMAX, typename Fin, typename Xout, int KIND>
@@ -805,6 +865,24 @@ hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, d
     }
 #undef TDS_BETA
     return hipGetLastError();
+}
+
+void batch_scan_shape(int32_t P, int32_t* per, int32_t* G, int32_t* lgR) {
+    // the fewest groups, a power of two Gp <= kScanBatchMaxGroups, whose
+    // blocks per group stay on the one-pass path (<= kScanMaxPerBatch); the
+    // workgroup then takes R = kScanBatchThreads / Gp right-hand sides, so
+    // small systems get many right-hand sides per workgroup and large ones
+    // many groups.  Past 32 x 16 interface rows the groups grow longer.
+    const int32_t nsep = P > 1 ? P - 1 : 1;
+    const int32_t need = (nsep + kScanMaxPerBatch - 1) / kScanMaxPerBatch;
+    int32_t gp = 1;
+    while (gp < need && gp < kScanBatchMaxGroups) gp *= 2;
+    const int32_t p = std::max<int32_t>(4, (nsep + gp - 1) / gp);
+    *per = p;
+    *G = (nsep + p - 1) / p;                 // <= gp
+    int32_t lg = 0;
+    while ((1 << (lg + 1)) * gp <= kScanBatchThreads) ++lg;
+    *lgR = lg;
 }
 
 void scan_shape(int32_t P, int32_t max_groups, int32_t* per, int32_t* G) {
@@ -919,8 +997,8 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
                         int32_t bucket, int mode, int passes, const KTime* tm, hipStream_t s) {
     if (items == 0) return hipSuccess;
     if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
-    if (items > INT32_MAX / kBetaWaves) return hipErrorInvalidValue;
-    const dim3 g((unsigned)(items * kBetaWaves));
+    if (items > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 g((unsigned)items);
     const bool f64in = (mode == TDS_F64);
     if (bucket == 32) {
         if (f64in)
@@ -936,7 +1014,7 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (scans > 0) {
-        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanRhs * kScanMaxGroups), 0, s,
+        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanBatchThreads), 0, s,
                  tm ? tm + 1 : nullptr, D, K);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
