@@ -287,3 +287,26 @@ def test_single_row_system():
     F = torch.tensor([[2.0, -8.0, 1.0]], dtype=torch.float64, device=DEV)
     X = plan.solve(F, mode="f64").cpu().numpy()
     assert np.allclose(X, [[0.5, -2.0, 0.25]], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("order", ["recurrence", "dense", "dichotomy"])
+def test_nonfinite_inputs_stay_in_their_column(order):
+    # every step works per right-hand side (the interface step mixes blocks,
+    # never columns), so a NaN or an infinity in one column of F leaves the
+    # other columns exactly as without it
+    rng = np.random.default_rng(31)
+    M, N, P = 1000, 300, 16
+    a, b = _rand(rng, M)
+    F = rng.uniform(-1, 1, size=(M, N))
+    Fbad = F.copy()
+    Fbad[123, 7] = np.nan
+    Fbad[900, 200] = np.inf
+    plan = t.Plan(a, b, P)
+    plan.set_interface(order)
+    clean = [c for c in range(N) if c not in (7, 200)]
+    for mode in ("f64", "f32_refined"):
+        dt = torch.float64 if mode == "f64" else torch.float32
+        X0 = plan.solve(torch.from_numpy(F).to(DEV).to(dt), mode=mode).cpu().numpy()
+        X1 = plan.solve(torch.from_numpy(Fbad).to(DEV).to(dt), mode=mode).cpu().numpy()
+        assert np.array_equal(X0[:, clean], X1[:, clean]), mode
+        assert not np.all(np.isfinite(X1[:, 7])) and not np.all(np.isfinite(X1[:, 200])), mode
