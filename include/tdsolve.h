@@ -41,7 +41,8 @@
  * F, X, gX, gF, ga, gb, and the output buffers of tdsolve_components and
  * tdsolve_residual are device pointers (the current HIP device) owned by
  * the caller.  X may equal F only when both have the same element type;
- * any other overlap is undefined.  A handle owns its device tables and a
+ * tdsolve_series and tdsolve_batch_series reject any other overlap of F and
+ * X (TDS_EINVAL).  A handle owns its device tables and a
  * work buffer that grows with N; calls on one handle must be ordered on a
  * single stream (use one handle per concurrent stream).
  *
@@ -119,9 +120,11 @@ int tdsolve_prepare_general(const double* lower, const double* diag,
 
 /* Solve the series (Algorithm 1 with Algorithm 3 step 2 for the interface
  * rows).  F: device [M][N] (double for TDS_F64, float otherwise).
- * X: device [M][N] (float for TDS_F32, double otherwise).  N >= 0 (N == 0
- * is a no-op; TDS_EUNSUPPORTED when N / 16 exceeds the launch grid,
- * 2^31 - 1).  Asynchronous on `stream`. */
+ * X: device [M][N] (float for TDS_F32, double otherwise).  X may be F
+ * itself when both have the same element type; any other overlap of the
+ * two arrays is TDS_EINVAL.  N >= 0 (N == 0 is a no-op; TDS_EUNSUPPORTED
+ * when N / 16 exceeds the launch grid, 2^31 - 1).  Asynchronous on
+ * `stream`. */
 int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N,
                    int32_t mode, void* stream);
 
@@ -162,6 +165,21 @@ int tdsolve_residual(tds_handle h, const void* F, const void* X, int64_t N,
  * [1] the interface step and [2] the block sweeps into ms (3 host doubles)
  * and the number of timed calls into *calls, then clears the record.  Keep
  * timing off while a stream is being captured into a graph. */
+/* Status of the handle's last series solve: an a-posteriori check of the
+ * accuracy the method guarantees for diagonally dominant A (Theorem 4).
+ * Synchronises `stream`, recomputes the residuals of the last
+ * tdsolve_series call (of every matrix of the last tdsolve_batch_series
+ * call, for a batch handle) from that call's F and X, which must still hold
+ * its input and result, and writes to *backward_err the largest normwise
+ * backward error max_n ||F_n - A X_n||_inf / (||A||_inf ||X_n||_inf +
+ * ||F_n||_inf) (NaN if any right-hand side gave a non-finite value; 0 for
+ * an empty call), and to *passes the refinement passes that call used (0
+ * unless TDS_F32_REFINED).  Either output may be NULL.  Allocates and frees
+ * a scratch buffer of about 5 M N / 64 doubles.  Errors: TDS_EINVAL (NULL
+ * handle, or no series call on it yet), TDS_ENOMEM, TDS_EHIP. */
+int tdsolve_status(tds_handle h, void* stream, double* backward_err,
+                   int32_t* passes);
+
 int tdsolve_timing_enable(tds_handle h, int32_t on);
 int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
 

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -37,6 +38,12 @@ struct tds_plan {
     std::vector<BatchDesc> desc;         // last descriptors uploaded
     BatchDesc* d_desc = nullptr;
     size_t desc_cap = 0;
+    // the last series call, for tdsolve_status
+    bool have_last = false;
+    int32_t last_mode = 0, last_passes = 0;
+    std::vector<const void*> last_F;
+    std::vector<const void*> last_X;
+    std::vector<int64_t> last_N;
 };
 
 namespace {
@@ -323,6 +330,32 @@ hipError_t zero_f64(double* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ||A||_inf from the host tables
+double norm_inf(const HostTables& o) {
+    double normA = 0.0;
+    for (int64_t i = 0; i < o.M; ++i) {
+        const double r = fabs(o.b64[i]) + (i > 0 ? fabs(o.l64[i - 1]) : 0.0) + fabs(o.a64[i]);
+        normA = std::max(normA, r);
+    }
+    return normA;
+}
+
+// F and X of one solve may be the same array, but not partly overlap
+bool overlap(const void* F, size_t fbytes, const void* X, size_t xbytes) {
+    const uintptr_t f0 = (uintptr_t)F, x0 = (uintptr_t)X;
+    return F != X && f0 < x0 + xbytes && x0 < f0 + fbytes;
+}
+
+void remember(tds_plan* h, const void* const* F, void* const* X, const int64_t* N, int32_t K,
+              int32_t mode) {
+    h->last_F.assign(F, F + K);
+    h->last_X.assign(X, X + K);
+    h->last_N.assign(N, N + K);
+    h->last_mode = mode;
+    h->last_passes = mode == TDS_F32_REFINED ? h->passes : 0;
+    h->have_last = true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -330,14 +363,7 @@ extern "C" {
 // checks, ||A||_inf and upload after the host tables are in place
 static int finish_plan(tds_plan* h, tds_handle* out) {
     if (h->host.P > 65535) { delete h; return TDS_EUNSUPPORTED; }
-    const int64_t M = h->host.M;
-    double normA = 0.0;
-    for (int64_t i = 0; i < M; ++i) {
-        double r = fabs(h->host.b64[i]) + (i > 0 ? fabs(h->host.l64[i - 1]) : 0.0) +
-                   fabs(h->host.a64[i]);
-        normA = std::max(normA, r);
-    }
-    h->normA = normA;
+    h->normA = norm_inf(h->host);
     const int rc = upload(h);
     if (rc) { delete h; return rc; }
     *out = h;
@@ -371,7 +397,14 @@ int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N, int32_t mode
     if (N == 0) return TDS_OK;
     if (!F || !X) return TDS_EINVAL;
     if (F == X && f_elem(mode) != x_elem(mode)) return TDS_EINVAL;
-    return series_impl(h, F, X, N, mode, (hipStream_t)stream, mode);
+    const size_t cells = (size_t)h->dev.M * (size_t)N;
+    if (overlap(F, cells * f_elem(mode), X, cells * x_elem(mode))) return TDS_EINVAL;
+    rc = series_impl(h, F, X, N, mode, (hipStream_t)stream, mode);
+    if (rc == TDS_OK) {
+        void* Xv = X;
+        remember(h, &F, &Xv, &N, 1, mode);
+    }
+    return rc;
 }
 
 int tdsolve_components(tds_handle h, const void* F, double* Xsep, int64_t N, int32_t mode,
@@ -651,6 +684,9 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         const int64_t n = N[k];
         if (n < 0 || (n > 0 && (!F[k] || !X[k]))) return TDS_EINVAL;
         if (n > 0 && F[k] == X[k] && f_elem(mode) != x_elem(mode)) return TDS_EINVAL;
+        const size_t cells = (size_t)t.M * (size_t)n;
+        if (n > 0 && overlap(F[k], cells * f_elem(mode), X[k], cells * x_elem(mode)))
+            return TDS_EINVAL;
         BatchDesc& d = desc[k];
         d.F = F[k];
         d.X = X[k];
@@ -670,7 +706,10 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
             if (t.P > 1) scans += (n + ((int64_t)1 << d.lgR) - 1) >> d.lgR;
         }
     }
-    if (items == 0) return TDS_OK;
+    if (items == 0) {
+        remember(h, F, X, N, K, mode);
+        return TDS_OK;
+    }
     if (items > 0x7fffffffLL || scans > 0x7fffffffLL) return TDS_EUNSUPPORTED;
     int rc = ensure_work(h, std::max<size_t>(bytes, 256));
     if (rc) return rc;
@@ -708,6 +747,61 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, tm,
                      (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
+    remember(h, F, X, N, K, mode);
+    return TDS_OK;
+}
+
+int tdsolve_status(tds_handle h, void* stream, double* backward_err, int32_t* passes) {
+    if (!h || !h->have_last) return TDS_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    const size_t K = h->last_N.size();
+    // scratch of the residual kernel (partial sums, then eta and r2 per RHS)
+    size_t need = 0;
+    for (size_t k = 0; k < K; ++k) {
+        const DevTables& t = h->is_batch ? h->devs[k] : h->dev;
+        const size_t n = (size_t)h->last_N[k];
+        const size_t chunks = (size_t)((t.M + kReduceRowChunk - 1) / kReduceRowChunk);
+        if (n > 0 && chunks > 65535) return TDS_EUNSUPPORTED;
+        need = std::max(need, 5 * chunks * n + 2 * n);
+    }
+    double worst = 0.0;
+    bool nonfinite = false;
+    if (need > 0) {
+        void* buf = nullptr;
+        const hipError_t e = hipMalloc(&buf, sizeof(double) * need);
+        if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
+        if (e != hipSuccess) return TDS_EHIP;
+        int rc = TDS_OK;
+        std::vector<double> eta;
+        for (size_t k = 0; k < K && rc == TDS_OK; ++k) {
+            const int64_t n = h->last_N[k];
+            if (n == 0) continue;
+            const DevTables& t = h->is_batch ? h->devs[k] : h->dev;
+            const size_t chunks = (size_t)((t.M + kReduceRowChunk - 1) / kReduceRowChunk);
+            double* part = (double*)buf;
+            double* out = part + 5 * chunks * (size_t)n;
+            const double normA = h->is_batch ? norm_inf(h->hosts[k]) : h->normA;
+            eta.resize((size_t)n);
+            if (launch_residual(t, h->last_F[k], h->last_X[k], n, h->last_mode, normA, part, out,
+                                s) != hipSuccess ||
+                hipMemcpyAsync(eta.data(), out, sizeof(double) * n, hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                rc = TDS_EHIP;
+                break;
+            }
+            for (double v : eta) {
+                if (!std::isfinite(v)) nonfinite = true;
+                else worst = std::max(worst, v);
+            }
+        }
+        (void)hipFree(buf);
+        if (rc) return rc;
+    } else if (hipStreamSynchronize(s) != hipSuccess) {
+        return TDS_EHIP;
+    }
+    if (backward_err) *backward_err = nonfinite ? NAN : worst;
+    if (passes) *passes = h->last_passes;
     return TDS_OK;
 }
 

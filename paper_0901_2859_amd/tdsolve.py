@@ -33,6 +33,7 @@ SYMBOLS = [
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
     "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
+    "tdsolve_status",
 ]
 
 _lib = None
@@ -80,6 +81,7 @@ def lib():
     L.tdsolve_strerror.restype = ctypes.c_char_p
     L.tdsolve_batch_prepare.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(vp)]
     L.tdsolve_batch_series.argtypes = [vp, vp, vp, vp, i32, vp]
+    L.tdsolve_status.argtypes = [vp, vp, vp, vp]
     L.tdsolve_timing_enable.argtypes = [vp, i32]
     L.tdsolve_timing_read.argtypes = [vp, vp, vp]
     L.tdsolve_autotune.argtypes = [dp, dp, i64, i64, i32, i32, vp, vp, vp]
@@ -168,6 +170,14 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _status(h, stream):
+    err = ctypes.c_double()
+    passes = ctypes.c_int32()
+    _check(lib().tdsolve_status(h, _stream_ptr(stream), ctypes.byref(err), ctypes.byref(passes)),
+           "tdsolve_status")
+    return float(err.value), int(passes.value)
+
+
 class Plan:
     """A prepared matrix (preliminary step of the method, done once)."""
 
@@ -219,6 +229,11 @@ class Plan:
         calls = np.zeros(1, dtype=np.int64)
         _check(lib().tdsolve_timing_read(self._h, _ptr(ms), _ptr(calls)), "tdsolve_timing_read")
         return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
+
+    def status(self, stream=None):
+        """(largest normwise backward error, refinement passes) of the last
+        solve; synchronises (tdsolve_status)."""
+        return _status(self._h, stream)
 
     def set_interface(self, order: str):
         """'recurrence' (default, Theorem 2 as two recurrences), 'dichotomy'
@@ -346,6 +361,11 @@ class BatchPlan:
         calls = np.zeros(1, dtype=np.int64)
         _check(lib().tdsolve_timing_read(self._h, _ptr(ms), _ptr(calls)), "tdsolve_timing_read")
         return float(ms[0]), float(ms[1]), float(ms[2]), int(calls[0])
+
+    def status(self, stream=None):
+        """(largest normwise backward error over all matrices, refinement
+        passes) of the last batch solve; synchronises (tdsolve_status)."""
+        return _status(self._h, stream)
 
     def solve(self, F_list, X_list=None, mode="f32_refined", stream=None):
         import torch

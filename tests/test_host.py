@@ -284,3 +284,12 @@ def test_dense_table_host_limits():
     assert err.value.code == -6                 # TDS_EUNSUPPORTED: P > 1024
     K = t.dense_table_host(a[:3], b[:4], 2)     # one interface row: both parts 1 at j = 0, 1
     assert np.array_equal(K, np.array([[1.0, 0.0, 0.0, 1.0]]))
+
+
+def test_status_and_overlap_checks_without_gpu():
+    # tdsolve_status needs a handle that has solved something; a NULL
+    # handle is rejected before any HIP call
+    L = t.lib()
+    err = ctypes.c_double()
+    passes = ctypes.c_int32()
+    assert L.tdsolve_status(None, None, ctypes.byref(err), ctypes.byref(passes)) == -1
