@@ -14,6 +14,7 @@ import ctypes
 import hashlib
 import json
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -519,6 +520,35 @@ def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
     return Ps.tolist(), ms.value
 
 
+# Plans of the differentiable solve, reused while a and b are the same
+# tensors with the same in-place version (weak references: a freed tensor,
+# or one whose storage address is reused, never matches).
+_PLAN_CACHE_SIZE = 8
+_plan_cache: list = []
+
+
+def _version(x):
+    return getattr(x, "_version", None)
+
+
+def cached_plan(a, b, P=None):
+    """A Plan for (a, b, P), taken from the cache while a and b are the same
+    objects, unmodified in place since the plan was made (torch tensors carry
+    an in-place version counter; other arrays are matched by identity only,
+    so they must not be modified in place between calls)."""
+    for ra, rb, va, vb, p, plan in reversed(_plan_cache):
+        if ra() is a and rb() is b and va == _version(a) and vb == _version(b) and p == P:
+            return plan
+    plan = Plan(a, b, P)
+    try:
+        entry = (weakref.ref(a), weakref.ref(b), _version(a), _version(b), P, plan)
+    except TypeError:                 # objects without weak references: no caching
+        return plan
+    _plan_cache.append(entry)
+    del _plan_cache[:-_PLAN_CACHE_SIZE]
+    return plan
+
+
 def _autograd_fn():
     import torch
 
@@ -530,7 +560,7 @@ def _autograd_fn():
 
         @staticmethod
         def forward(ctx, F, a, b, P=None, mode=None):
-            plan = Plan(a, b, P)
+            plan = cached_plan(a, b, P)
             m = mode_id(mode if mode is not None else ("f64" if F.dtype == torch.float64 else "f32_refined"))
             X = plan.solve(F.contiguous(), mode=m)
             ctx.plan, ctx.mode = plan, m

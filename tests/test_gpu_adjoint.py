@@ -123,3 +123,27 @@ def test_backward_fp32_mode():
     assert _nrel(gF.cpu().numpy(), gF_or) <= 1e-5
     assert _nrel(ga.cpu().numpy(), ga_or) <= 1e-4
     assert _nrel(gb.cpu().numpy(), gb_or) <= 1e-4
+
+
+def test_differentiable_solve_reuses_its_plan():
+    # the preliminary step runs once per (a, b); an in-place change of b (an
+    # optimizer step) makes a new plan whose solution follows the new b
+    rng = np.random.default_rng(17)
+    M, N, P = 600, 40, 8
+    a = -rng.uniform(0.5, 1.0, size=M - 1)
+    b = 3.0 + rng.uniform(0.0, 1.0, size=M)
+    at = torch.tensor(a, dtype=torch.float64, device=DEV, requires_grad=True)
+    bt = torch.tensor(b, dtype=torch.float64, device=DEV, requires_grad=True)
+    F = torch.from_numpy(rng.uniform(-1, 1, size=(M, N))).to(DEV)
+    p1 = t.cached_plan(at, bt, P)
+    assert t.cached_plan(at, bt, P) is p1
+    X1 = t.tdsolve(F, at, bt, P, "f64")
+    assert t.cached_plan(at, bt, P) is p1                      # forward used the cached plan
+    with torch.no_grad():
+        bt.add_(0.5)
+    p2 = t.cached_plan(at, bt, P)
+    assert p2 is not p1
+    X2 = t.tdsolve(F, at, bt, P, "f64").detach().cpu().numpy()
+    ref = oracle.thomas(a, b + 0.5, F.cpu().numpy())
+    assert np.max(np.abs(X2 - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert not torch.equal(X1.detach(), torch.from_numpy(X2).to(DEV))
