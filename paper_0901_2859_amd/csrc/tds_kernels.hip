@@ -775,11 +775,31 @@ __device__ __forceinline__ int32_t find_desc(const BatchDesc* __restrict__ D, in
     return lo;
 }
 
+// Item of a batch workgroup.  Workgroups are dispatched to the chip's 8
+// XCDs (each with its own L2) round-robin by index; consecutive items are
+// neighbouring tiles of one block, whose rows share cache lines at the tile
+// boundaries when N is not a multiple of 32 (F) or 16 (X).  Runs of
+// kXcdRun consecutive items go to one XCD, and the XCDs take the runs in
+// turn: most neighbours then share an L2, so such a line is fetched once,
+// while every XCD still works through the whole batch at the same pace (one
+// contiguous share per XCD removed the extra fetches but lost more to the
+// uneven cost of the shares).  A bijection of [0, gridDim.x): the last,
+// partial group of 8 runs keeps the plain order.
+constexpr uint32_t kXcds = 8;
+constexpr uint32_t kXcdRun = 8;
+__device__ __forceinline__ int64_t xcd_item() {
+    const uint32_t n = gridDim.x, x = blockIdx.x;
+    constexpr uint32_t span = kXcds * kXcdRun;
+    const uint32_t sup = x / span, within = x % span;
+    if ((uint64_t)(sup + 1) * span > n) return x;
+    return (int64_t)sup * span + (within % kXcds) * kXcdRun + within / kXcds;
+}
+
 // one workgroup per item: wavefront wv takes right-hand sides wv*64 .. +63
 // of the item's 256 (beta_rows_item)
 template <int TMAX, typename Fin>
 __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict__ D, int32_t K) {
-    const int64_t item = blockIdx.x;
+    const int64_t item = xcd_item();
     const int32_t k = find_desc(D, K, item, false);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
@@ -798,7 +818,7 @@ __global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
     // carries 2 G R + factors 2 G + S^R by row G per R, with G R <= 256
     __shared__ double S[2 * kScanBatchThreads + 2 * kScanBatchMaxGroups +
                         kScanBatchThreads * kScanMaxPerBatch];
-    const int64_t item = blockIdx.x;
+    const int64_t item = xcd_item();
     const int32_t k = find_desc(D, K, item, true);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.scan0;
@@ -811,7 +831,7 @@ template <int TMAX, typename Fin, typename Xout, int KIND>
 __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_batch(
     const BatchDesc* __restrict__ D, int32_t K, int passes) {
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
-    const int64_t item = blockIdx.x;
+    const int64_t item = xcd_item();
     const int32_t k = find_desc(D, K, item, false);
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
@@ -988,7 +1008,8 @@ static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, 
                      D, K, passes);
             break;
         default:
-            launch_k(k_sweep_batch<TM, float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D, K, passes);
+            launch_k(k_sweep_batch<TM, float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D,
+                     K, passes);
             break;
     }
 }
