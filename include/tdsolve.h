@@ -33,7 +33,9 @@
  *   TDS_F64          F double, X double; FP64 sweeps.
  *   TDS_F32_REFINED  F float,  X double; FP32 sweeps inside each block with
  *                    FP64 interface values and FP64 residual-based
- *                    refinement passes, all in registers (default 2 passes).
+ *                    refinement passes, all in registers (default 2 passes;
+ *                    blocks of more than 64 rows are swept in FP64
+ *                    arithmetic instead, as in TDS_F32_WIDE).
  *   TDS_F32          F float,  X float;  FP32 sweeps, FP64 interface step.
  *   TDS_F32_WIDE     F float,  X double; FP64 sweeps of the widened input.
  *

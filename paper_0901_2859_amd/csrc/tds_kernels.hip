@@ -960,6 +960,11 @@ static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, in
         TDS_SWEEP(64);
     else if (m <= kRegMaxRows && KIND != kSweepRefined)
         TDS_SWEEP(128);
+    else if (m <= kRegMaxRows)
+        // the refined sweep's registers hold 64-row blocks; longer ones take
+        // the register sweep in FP64 arithmetic (as accurate, no passes)
+        launch_k(k_sweep_reg<128, Fin, Xout, kSweep64, GEN>, g, dim3(kWG), 0, s, tm, t,
+                 (const Fin*)F, (Xout*)X, N, xsep, passes);
     else
         launch_k(k_sweep_stream<Fin, Xout, KIND == kSweep32 ? kSweep32 : kSweep64, GEN>, g,
                  dim3(kWG), 0, s, tm, t, (const Fin*)F, (Xout*)X, N, xsep);
