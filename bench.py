@@ -369,7 +369,7 @@ class Fourier:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
     import torch

@@ -71,7 +71,7 @@ typedef enum {
     TDS_ENOMEM = -3,        /* host or device allocation failed */
     TDS_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
     TDS_ENOCONV = -5,       /* reserved: refinement did not converge */
-    TDS_EUNSUPPORTED = -6   /* valid request this build does not handle */
+    TDS_EUNSUPPORTED = -6   /* valid request outside what the library handles */
 } tds_status;
 
 typedef enum {
