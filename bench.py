@@ -57,6 +57,10 @@ def parse():
     p.add_argument("--M", type=int, default=0)
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
+    p.add_argument("--passes", type=int, default=None,
+                   help="refinement passes of the f32_refined mode; default: the fewest that "
+                        "reach the residual of more passes on the workload (measured): 1 for "
+                        "the Poisson series, 2 (the library default) for the others")
     p.add_argument("--interface", default="auto",
                    choices=["auto", "recurrence", "dichotomy", "dense"],
                    help="evaluation order of the interface values (single-matrix workloads); "
@@ -146,6 +150,7 @@ class Single:
         if order == "auto":
             order = "dense" if P <= 64 else "recurrence"
         self.plan.set_interface(order)
+        self.plan.set_refinement(args.passes)
         self.unknowns = M * N
         self.config = {"workload": self.name, "M": M, "N": N, "P": P, "interface": order}
 
@@ -213,6 +218,7 @@ class Batch:
         self.P, self.tune_ms = t.batch_autotune(self.a, self.b, self.Ns, args.mode)
         t0 = time.perf_counter()
         self.plan = t.BatchPlan(self.a, self.b, self.P)
+        self.plan.set_refinement(args.passes)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
         self.unknowns = sum(m * n for m, n in zip(self.Ms, self.Ns))
@@ -276,6 +282,7 @@ class Gradient(Single):
         self.a, self.b, self.F32, self.W = w["a"], w["b"], w["F"], w["W"]
         t0 = time.perf_counter()
         self.plan = t.Plan(self.a, self.b, self.P)
+        self.plan.set_refinement(args.passes)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
         self.unknowns = self.M * self.N
@@ -327,6 +334,7 @@ class Fourier:
     def solver(self, mode):
         if mode not in self.solvers:
             self.solvers[mode] = self.cls(self.n, self.n, self.S, mode=mode)
+            self.solvers[mode].plan.set_refinement(self.args.passes)
         return self.solvers[mode]
 
     def sweep_bytes(self, mode):
@@ -368,6 +376,8 @@ class Fourier:
 
 def main():
     args = parse()
+    if args.passes is None:
+        args.passes = 1 if args.workload == "poisson" else 2
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; run with --gpus 1"}))
         sys.exit(2)
@@ -438,7 +448,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.mode],
         "data": "synthetic",
-        "config": dict(W.config, mode=args.mode, layout="RHS-interleaved [M][N]",
+        "config": dict(W.config, mode=args.mode, refine_passes=args.passes,
+                       layout="RHS-interleaved [M][N]",
                        buffer_sets=main_r["sets"], launch=main_r["launch"]),
         "hbm_frac_path": round(main_r["path_gbs"] / HBM_PEAK_GBS, 4),
         "path_gbs": round(main_r["path_gbs"], 1),

@@ -368,6 +368,9 @@ class BatchPlan:
         passes) of the last batch solve; synchronises (tdsolve_status)."""
         return _status(self._h, stream)
 
+    def set_refinement(self, passes: int):
+        _check(lib().tdsolve_set_refinement(self._h, int(passes)), "tdsolve_set_refinement")
+
     def solve(self, F_list, X_list=None, mode="f32_refined", stream=None):
         import torch
         m = mode_id(mode)
