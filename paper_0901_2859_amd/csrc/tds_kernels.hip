@@ -13,16 +13,18 @@
 // when their pointers come from a descriptor table, as in the batch.)
 //
 //   beta   eq. beta_symn: beta^R_j, beta^L_j of block j (FP64 accumulation).
-//   iface  Theorem 2 (eq. theor_2): x at the interface rows by the two
-//          first-order recurrences S^R_{k+1} = rho_k S^R_k + beta^R_k and
-//          S^L_k = beta^L_k + lam_k S^L_{k+1}, x(s_k) = S^R_k + S^L_k.
+//   iface  Theorem 2 (eq. theor_2): x at the interface rows, in one of three
+//          orders: the two first-order recurrences S^R_{k+1} = rho_k S^R_k +
+//          beta^R_k and S^L_k = beta^L_k + lam_k S^L_{k+1}, x(s_k) = S^R_k +
+//          S^L_k (default); Algorithm 4's dichotomy, level by level; or the
+//          double sum itself as one dense product on the FP64 matrix cores.
 //   sweep  Lemma 1 / Algorithm 1 step 3: the sweep inside each block with
-//          both boundary values known.
+//          both boundary values known; X leaves with streaming stores.
 //
 // Each step is a device function over one work item; the single-matrix
 // kernels index items by their 2-D grid, the batch kernels (many matrices of
 // uneven sizes in one launch per step) find their matrix and item in a
-// descriptor table.
+// descriptor table, in an XCD-aware item order.
 #include <type_traits>
 
 #include <hip/hip_ext.h>
