@@ -30,15 +30,20 @@ import numpy as np
 from . import tdsolve as t
 
 
-def dst1(x):
-    """Type-I sine transform along the last axis: y_l = sum_j x_j
-    sin(pi l j / (m + 1)), l, j = 1..m, via the FFT of the odd extension of
-    length 2 (m + 1)."""
+def _dst1_view(x):
+    """-y of the type-I sine transform along the last axis, as a strided view:
+    y_l = sum_j x_j sin(pi l j / (m + 1)) = -Im sum_j x_j exp(-i pi l j /
+    (m + 1)), the real FFT of length 2 (m + 1) of x placed at positions
+    1..m (one padded copy; x may be any strided view)."""
     import torch
     m = x.shape[-1]
-    z = torch.zeros(x.shape[:-1] + (1,), dtype=x.dtype, device=x.device)
-    ext = torch.cat([z, x, z, -torch.flip(x, dims=[-1])], dim=-1)
-    return -torch.fft.rfft(ext, dim=-1).imag[..., 1:m + 1] / 2
+    return torch.fft.rfft(torch.nn.functional.pad(x, (1, m + 1)), dim=-1).imag[..., 1:m + 1]
+
+
+def dst1(x):
+    """Type-I sine transform along the last axis: y_l = sum_j x_j
+    sin(pi l j / (m + 1)), l, j = 1..m."""
+    return -_dst1_view(x)
 
 
 class FourierPoisson2D:
@@ -80,13 +85,14 @@ class FourierPoisson2D:
         if tuple(f.shape) != (S, M, L):
             raise ValueError(f"f must have shape {(S, M, L)}")
         wdt = torch.float64 if self.mode == "f64" else torch.float32
-        # harmonics of f along y, scaled to the right-hand side h1^2 f~(l)
+        # harmonics of f along y, scaled to the right-hand side h1^2 f~(l) and
+        # written straight into the RHS-interleaved layout (l, i, S) by one
+        # strided multiply (scale and transpose in one pass)
         scale = self.h1 ** 2 * 2.0 / self.N2
-        fl = dst1(f.to(wdt)) * scale                          # (S, i, l)
-        rhs = fl.permute(2, 1, 0).contiguous()               # (l, i, S): RHS-interleaved
+        rhs = torch.empty((L, M, S), dtype=wdt, device=f.device)
+        torch.mul(_dst1_view(f.to(wdt)), -scale, out=rhs.permute(2, 1, 0))
         X = self.plan.solve_stacked(rhs, mode=self.mode, stream=stream)
-        ul = X.permute(2, 1, 0)                               # (S, i, l)
-        return dst1(ul.contiguous())                          # back to mesh values in y
+        return dst1(X.permute(2, 1, 0))                       # back to mesh values in y
 
     @staticmethod
     def eigen_rhs(N1, N2, k, l, h1=None, h2=None):
