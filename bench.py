@@ -414,7 +414,12 @@ def main():
     ms_sweep = main_r["ms_sweep"]
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
     batched = args.workload in ("batch", "fourier")
-    kname = "k_sweep_batch" if batched else "k_sweep_reg"
+    if batched:
+        kname = "k_sweep_batch"
+    elif args.mode == "f32_refined" and W.plan.info().refined_halves:
+        kname = "k_sweep_halves"
+    else:
+        kname = "k_sweep_reg"
     shape = (args.workload if batched else f"{args.workload}_{W.M}x{W.N}_P{W.P}")
     # HBM bytes per launch measured by rocprofv3 counters for this kernel,
     # mode and workload; null unless taken from the current kernel sources

@@ -17,6 +17,9 @@ using namespace tds;
 struct tds_plan {
     HostTables host;
     DevTables dev;
+    // the refined sweep's half-block tables (half_tables), when the blocks fit
+    bool has_halves = false;
+    DevTables halves;
     void* dev_mem = nullptr;
     double normA = 0.0;          // ||A||_inf
     int32_t passes = 2;          // refinement passes of TDS_F32_REFINED
@@ -35,6 +38,7 @@ struct tds_plan {
     int32_t bucket = 0;                  // common register-sweep row bucket
     std::vector<HostTables> hosts;
     std::vector<DevTables> devs;
+    std::vector<DevTables> devs_h;       // half-block tables, when every matrix has them
     std::vector<BatchDesc> desc;         // last descriptors uploaded
     BatchDesc* d_desc = nullptr;
     size_t desc_cap = 0;
@@ -73,6 +77,7 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     const size_t o_v = take(sizeof(double) * MR);
     const size_t o_a32 = take(sizeof(float) * MR), o_cp32 = take(sizeof(float) * MR);
     const size_t o_rd32 = take(sizeof(float) * MR), o_in32 = take(sizeof(float) * MR);
+    const size_t o_mid = take(sizeof(double) * P);
     img.resize(off, 0);
 
     auto put = [&](size_t at, const void* src, size_t bytes) { memcpy(img.data() + at, src, bytes); };
@@ -123,6 +128,7 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     pad32(o_cp32, o.cp64, 0.0f);
     pad32(o_rd32, o.rd64, 1.0f);
     pad32(o_in32, in, 0.0f);
+    if (!o.mid_inv.empty()) put(o_mid, o.mid_inv.data(), sizeof(double) * P);
 
     DevTables d;
     d.M = M;
@@ -151,6 +157,7 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     d.cp32 = (float*)o_cp32;
     d.rd32 = (float*)o_rd32;
     d.in32 = (float*)o_in32;
+    d.mid_inv = (double*)o_mid;
     return d;
 }
 
@@ -166,6 +173,7 @@ void rebase(DevTables& d, void* mem) {
     shift(d.in64, b); shift(d.u, b); shift(d.v, b); shift(d.a32, b); shift(d.cp32, b);
     shift(d.rd32, b); shift(d.in32, b);
     shift(d.l64, b); shift(d.inl64, b); shift(d.l32, b); shift(d.inl32, b);
+    shift(d.mid_inv, b);
 }
 
 int upload_image(const std::vector<unsigned char>& img, void** out) {
@@ -185,9 +193,15 @@ int upload(tds_plan* h) {
     if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
     std::vector<unsigned char> img;
     h->dev = append_image(h->host, rows_bucket(h->host.max_rows), img);
+    // blocks of 33..64 rows: the refined sweep takes them in halves
+    HostTables hh;
+    h->has_halves = rows_bucket(h->host.max_rows) == 64 &&
+                    half_tables(h->host, kHalfRows, hh) == TDS_OK;
+    if (h->has_halves) h->halves = append_image(hh, 0, img);
     int rc = upload_image(img, &h->dev_mem);
     if (rc) return rc;
     rebase(h->dev, h->dev_mem);
+    if (h->has_halves) rebase(h->halves, h->dev_mem);
     return TDS_OK;
 }
 
@@ -300,8 +314,8 @@ int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hi
         empty_phase(h, 1);
     }
     if (N > 0) {
-        if (launch_sweep(t, F, X, N, sweep_mode, h->passes, xsep, s, tm ? tm + 2 : nullptr) !=
-            hipSuccess)
+        if (launch_sweep(t, F, X, N, sweep_mode, h->passes, xsep, s, tm ? tm + 2 : nullptr,
+                         h->has_halves ? &h->halves : nullptr) != hipSuccess)
             return TDS_EHIP;
     } else if (tm) {
         empty_phase(h, 2);
@@ -560,6 +574,7 @@ int tdsolve_info(tds_handle h, tds_info* info) {
     info->refine_passes = h->passes;
     info->max_ratio = h->host.max_ratio;
     info->general = h->host.general;
+    info->refined_halves = h->has_halves ? 1 : 0;
     return TDS_OK;
 }
 
@@ -664,9 +679,20 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a, const double* const
     std::vector<unsigned char> img;
     h->devs.resize(K);
     for (int32_t k = 0; k < K; ++k) h->devs[k] = append_image(h->hosts[k], bucket, img);
+    // 64-row bucket: the refined sweep takes the blocks in halves when every
+    // matrix's blocks fit them (one sweep kernel for the whole batch)
+    h->has_halves = bucket == 64;
+    std::vector<HostTables> hh(h->has_halves ? K : 0);
+    for (int32_t k = 0; k < K && h->has_halves; ++k)
+        h->has_halves = half_tables(h->hosts[k], kHalfRows, hh[k]) == TDS_OK;
+    if (h->has_halves) {
+        h->devs_h.resize(K);
+        for (int32_t k = 0; k < K; ++k) h->devs_h[k] = append_image(hh[k], 0, img);
+    }
     int rc = upload_image(img, &h->dev_mem);
     if (rc) { delete h; return rc; }
     for (int32_t k = 0; k < K; ++k) rebase(h->devs[k], h->dev_mem);
+    for (auto& d : h->devs_h) rebase(d, h->dev_mem);
     *out = h;
     return TDS_OK;
 }
@@ -692,6 +718,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         d.X = X[k];
         d.N = n;
         d.T = t;
+        d.H = h->has_halves ? h->devs_h[k] : DevTables();
         d.item0 = items;
         d.scan0 = scans;
         batch_scan_shape(t.P, &d.per, &d.G, &d.lgR);
@@ -744,7 +771,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     KTime* tm = timing_slot(h);
     if (h->timing && !tm) return TDS_EHIP;
     if (tm && scans == 0) empty_phase(h, 1);
-    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, tm,
+    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, h->has_halves, tm,
                      (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
     remember(h, F, X, N, K, mode);

@@ -57,6 +57,9 @@ struct DevTables {
     float* l32 = nullptr;
     float* cp32 = nullptr;
     float* rd32 = nullptr;
+    // tables of a half-block partition (half_tables): entry 2j+1 holds
+    // 1 / (Schur complement of block j's middle row); P entries
+    double* mid_inv = nullptr;
 };
 
 // Host-side FP64 preliminary step.  Returns a tds_status code.
@@ -70,6 +73,7 @@ struct HostTables {
     std::vector<double> wR, wL, rho, lam, diag_inv, a64, b64, cp64, rd64, u, v;
     std::vector<double> l64;               // sub-diagonal (a copy of a64 if symmetric)
     int32_t general = 0;                   // 1: non-symmetric A (by similarity)
+    std::vector<double> mid_inv;           // half-block partitions only (half_tables)
 };
 
 int host_prepare(const double* a, const double* b, int64_t M, int32_t P,
@@ -81,6 +85,15 @@ int32_t default_blocks(int64_t M);
 // 2 P (P-1) doubles (16 MB at 1024) and its work grows as P^2 per
 // right-hand side.
 constexpr int32_t kDenseMaxBlocks = 1024;
+// Rows of the left half when the refined sweep splits a block in two
+// (k_sweep_halves): blocks of kHalfRows + 2 .. 2 kHalfRows + 1 interior rows.
+constexpr int32_t kHalfRows = 32;
+// The partition with every block of `o` split into a left half of `lead`
+// interior rows, a middle row and a right half (at least one row), as
+// tables for the block sweeps: 2P segments whose interface rows are the
+// method's s_k and the middle rows, plus mid_inv.  TDS_EUNSUPPORTED when a
+// block's length is outside lead + 2 .. 2 lead + 1 interior rows.
+int half_tables(const HostTables& o, int32_t lead, HostTables& h);
 // Theorem 2's coefficients as one matrix for the dense interface order
 // (layout in tds_prepare.cpp); Pc, Mr: padded part width and row count.
 int dense_interface_table(const HostTables& o, std::vector<double>& Kt, int32_t* Pc,
@@ -112,9 +125,12 @@ hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR,
 hipError_t launch_iface_dense(const double* Kt, int32_t Pc, int32_t Mr, int32_t P,
                               const double* betaR, const double* betaL, double* xsep, int64_t N,
                               hipStream_t s, const KTime* tm = nullptr);
+// `halves` (may be null): the half-block tables of t (half_tables), used by
+// the refined sweep of blocks that fit them
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         int mode, int passes, const double* xsep,
-                        hipStream_t s, const KTime* tm = nullptr);
+                        hipStream_t s, const KTime* tm = nullptr,
+                        const DevTables* halves = nullptr);
 
 // register-sweep row bucket (32, 64, 128) of a largest block size, 0 if the
 // streaming sweep is needed
@@ -145,16 +161,19 @@ struct BatchDesc {
     int32_t G;
     int32_t lgR;
     int32_t pad_;
+    DevTables H;       // half-block tables (half_tables), when the batch uses them
 };
 
 // The three steps for all matrices of a batch: one launch each.  `bucket`
-// is the common register-sweep row bucket (32 or 64).
+// is the common register-sweep row bucket (32 or 64); `halves`: every
+// matrix's BatchDesc::H holds its half-block tables (bucket 64), and the
+// refined sweep takes the blocks in halves.
 // `tm` (may be null): start/stop events of the beta, interface and sweep
 // launches, in that order (the interface pair stays unrecorded when no
 // matrix has interface rows, scans == 0).
 hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items,
                         int64_t scans, int32_t bucket, int mode, int passes,
-                        const KTime* tm, hipStream_t s);
+                        bool halves, const KTime* tm, hipStream_t s);
 
 // uniform[-1, 1) values from a counter-based generator (timing inputs)
 hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipStream_t s);

@@ -523,6 +523,69 @@ __device__ __forceinline__ void sweep_load(const Fin* __restrict__ fb, int lane,
     for (int r = 0; r < TMAX; ++r) f[r] = (fb + (int64_t)(r < cnt ? r : cnt - 1) * N)[lane];
 }
 
+// Zero-boundary solve of one block (or half block) of the refined sweep:
+// x0 = T^{-1} f by an FP32 sweep, then `passes` times FP64 residual -> FP32
+// sweep of the residual -> FP64 update.  T's tables are read from row i0;
+// my_f holds the lane's FP32 right-hand side in LDS (row r at
+// my_f[r * STRIDE], STRIDE = the workgroup's lanes).
+template <int TMAX, bool GEN, int STRIDE = kWG>
+__device__ __forceinline__ void refined_solve(const DevTables& T, int64_t i0,
+                                              const float* __restrict__ my_f, int passes,
+                                              double (&x)[TMAX]) {
+    const cptr<double> b64 = cst(T.b64 + i0);
+    const cptr<float> cp32 = cst(T.cp32 + i0), rd32 = cst(T.rd32 + i0);
+    const cptr<float> inl32 = cst((GEN ? T.inl32 : T.in32) + i0);
+    float w[TMAX];
+#pragma unroll
+    for (int r = 0; r < TMAX; ++r) {
+        if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+        const float prev = (r > 0) ? w[r - 1] : 0.0f;
+        const float sub = (r > 0) ? inl32[r - 1] : 0.0f;
+        w[r] = (my_f[r * STRIDE] - sub * prev) * rd32[r];
+    }
+    {
+        float xs = 0.0f;
+#pragma unroll
+        for (int r = TMAX - 1; r >= 0; --r) {
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            xs = w[r] - cp32[r] * xs;
+            x[r] = (double)xs;
+        }
+    }
+    for (int p = 0; p < passes; ++p) {
+        // keep the LDS reads of F and the table loads inside the pass:
+        // an offset the compiler cannot see through stops it from
+        // hoisting every row's coefficients out of the loop
+        asm volatile("" ::: "memory");
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        const cptr<double> in64p = cst(T.in64 + i0) + z;
+        const cptr<double> inl64p = GEN ? cst(T.inl64 + i0) + z : in64p;
+        const cptr<double> b64p = b64 + z;
+        const cptr<float> inl32p = inl32 + z, cp32p = cp32 + z, rd32p = rd32 + z;
+#pragma unroll
+        for (int r = 0; r < TMAX; ++r) {
+            // bound the scheduler's look-ahead: the residuals do not
+            // depend on the elimination chain, and computing them all
+            // ahead of it would hold 64 FP64 values in registers
+            if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+            double res = (double)my_f[r * STRIDE] - b64p[r] * x[r];
+            if (r > 0) res -= inl64p[r - 1] * x[r - 1];
+            if (r + 1 < TMAX) res -= in64p[r] * x[r + 1];
+            const float prev = (r > 0) ? w[r - 1] : 0.0f;
+            const float sub = (r > 0) ? inl32p[r - 1] : 0.0f;
+            w[r] = ((float)res - sub * prev) * rd32p[r];
+        }
+        float dl = 0.0f;
+#pragma unroll
+        for (int r = TMAX - 1; r >= 0; --r) {
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            dl = w[r] - cp32p[r] * dl;
+            x[r] += (double)dl;
+        }
+    }
+}
+
 template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
 __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restrict__ xb, int lane,
                                            int64_t N, int cnt, double cl, double xl, double cr,
@@ -530,7 +593,7 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
                                            float* __restrict__ my_f, int passes) {
     // sub-diagonal: its own table for a non-symmetric A, else the one
     // off-diagonal table (one scalar stream fewer per row)
-    const cptr<double> l64 = cst((GEN ? T.l64 : T.a64) + i0), b64 = cst(T.b64 + i0);
+    const cptr<double> l64 = cst((GEN ? T.l64 : T.a64) + i0);
     const cptr<double> cp64 = cst(T.cp64 + i0), rd64 = cst(T.rd64 + i0);
     const cptr<double> uu = cst(T.u + i0), vv = cst(T.v + i0);
     const cptr<float> l32 = cst((GEN ? T.l32 : T.a32) + i0), cp32 = cst(T.cp32 + i0),
@@ -577,64 +640,14 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
         }
     } else {
         // Refined: the block is solved with zero boundary values, x0 =
-        // T^{-1} f, by an FP32 sweep and then `passes` times FP64 residual
-        // -> FP32 sweep of the residual -> FP64 update; the interface values
-        // enter at the end by superposition, x = x0 + xl u + xr v.  (With
-        // the boundary terms inside the right-hand side every pass would
-        // carry a row-dependent condition.)
+        // T^{-1} f (refined_solve); the interface values enter at the end by
+        // superposition, x = x0 + xl u + xr v.  (With the boundary terms
+        // inside the right-hand side every pass would carry a row-dependent
+        // condition.)
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) my_f[r * kWG] = (float)f[r];
-        const cptr<float> inl32 = cst((GEN ? T.inl32 : T.in32) + i0);
         double x[TMAX];
-        float w[TMAX];
-#pragma unroll
-        for (int r = 0; r < TMAX; ++r) {
-            if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
-            const float prev = (r > 0) ? w[r - 1] : 0.0f;
-            const float sub = (r > 0) ? inl32[r - 1] : 0.0f;
-            w[r] = (my_f[r * kWG] - sub * prev) * rd32[r];
-        }
-        {
-            float xs = 0.0f;
-#pragma unroll
-            for (int r = TMAX - 1; r >= 0; --r) {
-                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                xs = w[r] - cp32[r] * xs;
-                x[r] = (double)xs;
-            }
-        }
-        for (int p = 0; p < passes; ++p) {
-            // keep the LDS reads of F and the table loads inside the pass:
-            // an offset the compiler cannot see through stops it from
-            // hoisting every row's coefficients out of the loop
-            asm volatile("" ::: "memory");
-            int z;
-            asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-            const cptr<double> in64p = cst(T.in64 + i0) + z;
-            const cptr<double> inl64p = GEN ? cst(T.inl64 + i0) + z : in64p;
-            const cptr<double> b64p = b64 + z;
-            const cptr<float> inl32p = inl32 + z, cp32p = cp32 + z, rd32p = rd32 + z;
-#pragma unroll
-            for (int r = 0; r < TMAX; ++r) {
-                // bound the scheduler's look-ahead: the residuals do not
-                // depend on the elimination chain, and computing them all
-                // ahead of it would hold 64 FP64 values in registers
-                if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
-                double res = (double)my_f[r * kWG] - b64p[r] * x[r];
-                if (r > 0) res -= inl64p[r - 1] * x[r - 1];
-                if (r + 1 < TMAX) res -= in64p[r] * x[r + 1];
-                const float prev = (r > 0) ? w[r - 1] : 0.0f;
-                const float sub = (r > 0) ? inl32p[r - 1] : 0.0f;
-                w[r] = ((float)res - sub * prev) * rd32p[r];
-            }
-            float dl = 0.0f;
-#pragma unroll
-            for (int r = TMAX - 1; r >= 0; --r) {
-                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                dl = w[r] - cp32p[r] * dl;
-                x[r] += (double)dl;
-            }
-        }
+        refined_solve<TMAX, GEN>(T, i0, my_f, passes, x);
 #pragma unroll
         for (int r = 0; r < TMAX; ++r)
             if (r < cnt)
@@ -750,6 +763,88 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
                                       passes, s_f);
 }
 
+// Refined sweep of a block in two halves (tables from half_tables): block
+// j's interior rows i0..i1 are a left half of kHalfRows rows, the middle
+// row m = i0 + kHalfRows and a right half m+1..i1.  Wavefronts 0-1 take the
+// left half of 128 right-hand sides, wavefronts 2-3 the right half of the
+// same ones (RHS = 128; with RHS = 256, 8 wavefronts of which 0-3 take the
+// left half); each half is solved with zero boundary values (refined_solve).
+// The value at m then follows from row m's equation with its neighbours
+// written by superposition (x_{m-1} through the left half, x_{m+1} through
+// the right one):
+//     x_m = (f_m - A[m][m-1] qA - A[m][m+1] qB) mid_inv,
+//     qA = x0_{m-1} + x(s_j) u_{m-1},  qB = x0_{m+1} + x(s_{j+1}) v_{m+1},
+// where each half contributes its term through LDS and both evaluate the
+// same expression (bitwise the same x_m).  Each lane keeps half the rows of
+// the whole-block sweep: 4 wavefronts per SIMD instead of 2, which overlap
+// their loads, passes and stores.
+constexpr int kHalfRhs = 128;        // right-hand sides per workgroup (single matrix)
+
+// one work item of the halves sweep: block j of H's method partition (H.P / 2
+// blocks) x RHS right-hand sides from tile * RHS, on 2 RHS threads; s_f:
+// kHalfRows x 2 RHS floats, s_q: 2 RHS doubles of LDS
+template <int RHS, bool GEN>
+__device__ __forceinline__ void halves_item(const DevTables& H, const float* __restrict__ F,
+                                            double* __restrict__ X, int64_t N, int32_t j,
+                                            int64_t tile, const double* __restrict__ xsep,
+                                            int passes, float* s_f, double* s_q) {
+    constexpr int TM = kHalfRows, NT = 2 * RHS;
+    const int32_t P = H.P >> 1;                 // blocks of the method's partition
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / RHS);   // 0 left, 1 right
+    const int c = threadIdx.x % RHS;
+    const int64_t n0 = tile * RHS;
+    const bool live = n0 + c < N;
+    // lanes past N stay for the barrier and re-read the tile's last column
+    const int lane = live ? c : (int)(N - 1 - n0);
+    const int32_t js = 2 * j + h;
+    const int64_t seg_lo = cst(H.starts)[js], seg_hi = cst(H.starts)[js + 1];
+    const int64_t i0 = (js == 0) ? seg_lo : seg_lo + 1;
+    const int cnt = (int)(seg_hi - i0);         // TM on the left, 1..TM on the right
+    // the block's outer boundary value on this half's side
+    double xo = 0.0;
+    if (h == 0 && j > 0) xo = xsep[(int64_t)(j - 1) * N + n0 + lane];
+    if (h == 1 && j < P - 1) xo = xsep[(int64_t)j * N + n0 + lane];
+    float f[TM];
+    sweep_load<TM, float>(F + i0 * N + n0, lane, N, cnt, f);
+    float fm = 0.0f;
+    if (h == 0) fm = (F + seg_hi * N + n0)[lane];     // row m
+    float* my_f = s_f + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < TM; ++r) my_f[r * NT] = f[r];
+    double x[TM];
+    refined_solve<TM, GEN, NT>(H, i0, my_f, passes, x);
+    const cptr<double> uu = cst(H.u + i0), vv = cst(H.v + i0);
+    if (h == 0)
+        s_q[c] = (double)fm - cst(GEN ? H.l64 : H.a64)[seg_hi - 1] * fma(xo, uu[TM - 1], x[TM - 1]);
+    else
+        s_q[RHS + c] = fma(xo, vv[0], x[0]);
+    __syncthreads();
+    const int64_t m = cst(H.starts)[2 * j + 1];
+    const double xm = (s_q[c] - cst(H.a64)[m] * s_q[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
+    if (!live) return;
+    const double xl = h ? xm : xo, xr = h ? xo : xm;
+    double* xb = X + i0 * N + n0;
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+        if (r < cnt) store_x(&(xb + (int64_t)r * N)[c], fma(xr, vv[r], fma(xl, uu[r], x[r])));
+    if (h == 0) {
+        store_x(&X[m * N + n0 + c], xm);
+        if (j > 0) store_x(&X[seg_lo * N + n0 + c], xo);
+    }
+}
+
+template <int RHS, bool GEN>
+__global__ __launch_bounds__(2 * RHS, 4) void k_sweep_halves(DevTables H,
+                                                             const float* __restrict__ F,
+                                                             double* __restrict__ X, int64_t N,
+                                                             const double* __restrict__ xsep,
+                                                             int passes) {
+    __shared__ float s_f[kHalfRows * 2 * RHS];
+    __shared__ double s_q[2 * RHS];
+    halves_item<RHS, GEN>(H, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, xsep, passes,
+                          s_f, s_q);
+}
+
 template <typename Fin, typename Xout, int KIND, bool GEN>
 __global__ __launch_bounds__(kWG) void k_sweep_stream(DevTables T, const Fin* __restrict__ F,
                                                       Xout* __restrict__ X, int64_t N,
@@ -842,6 +937,23 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     sweep_item<TMAX, Fin, Xout, KIND, false>(d.T, (const Fin*)d.F, (Xout*)d.X, d.N,
                                       (int32_t)(local / tiles), local % tiles, d.xsep, passes,
                                       s_f);
+}
+
+// the batch's refined sweep when every matrix takes its blocks in halves
+// (BatchDesc::H): one workgroup of 2 x 256 threads per item, the item
+// structure of k_sweep_batch
+__global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDesc* __restrict__ D,
+                                                                   int32_t K, int passes) {
+    __shared__ float s_f[kHalfRows * 2 * kWG];
+    __shared__ double s_q[2 * kWG];
+    const int64_t item = xcd_item();
+    const int32_t k = find_desc(D, K, item, false);
+    const BatchDesc d = D[k];    // uniform, before any store: scalar loads
+    const int64_t local = item - d.item0;
+    const int64_t tiles = (d.N + kWG - 1) / kWG;
+    if (local >= (int64_t)d.T.P * tiles) return;        // uniform per workgroup
+    halves_item<kWG, false>(d.H, (const float*)d.F, (double*)d.X, d.N, (int32_t)(local / tiles),
+                            local % tiles, d.xsep, passes, s_f, s_q);
 }
 
 // ==========================================================================
@@ -948,9 +1060,18 @@ hipError_t launch_iface_dichotomy(const DevTables& t, const double* betaR, const
 
 template <typename Fin, typename Xout, int KIND, bool GEN>
 static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, int passes,
-                       const double* xsep, hipStream_t s, const KTime* tm) {
+                       const double* xsep, hipStream_t s, const KTime* tm,
+                       const DevTables* halves) {
     const int m = t.max_rows;
     const dim3 g = grid2(N, t.P);
+    if constexpr (KIND == kSweepRefined) {
+        if (halves && m > kHalfRows && m <= 2 * kHalfRows && halves->P == 2 * t.P) {
+            launch_k(k_sweep_halves<kHalfRhs, GEN>,
+                     dim3((unsigned)((N + kHalfRhs - 1) / kHalfRhs), t.P, 1), dim3(2 * kHalfRhs),
+                     0, s, tm, *halves, (const float*)F, (double*)X, N, xsep, passes);
+            return;
+        }
+    }
 #define TDS_SWEEP(TM)                                                                   \
     launch_k(k_sweep_reg<TM, Fin, Xout, KIND, GEN>, g, dim3(kWG), 0, s, tm, t, (const Fin*)F, \
              (Xout*)X, N, xsep, passes)
@@ -975,22 +1096,30 @@ static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, in
 
 template <typename Fin, typename Xout, int KIND>
 static void go_sweep(const DevTables& t, const void* F, void* X, int64_t N, int passes,
-                     const double* xsep, hipStream_t s, const KTime* tm) {
+                     const double* xsep, hipStream_t s, const KTime* tm,
+                     const DevTables* halves) {
     if (t.general)
-        go_sweep_t<Fin, Xout, KIND, true>(t, F, X, N, passes, xsep, s, tm);
+        go_sweep_t<Fin, Xout, KIND, true>(t, F, X, N, passes, xsep, s, tm, halves);
     else
-        go_sweep_t<Fin, Xout, KIND, false>(t, F, X, N, passes, xsep, s, tm);
+        go_sweep_t<Fin, Xout, KIND, false>(t, F, X, N, passes, xsep, s, tm, halves);
 }
 
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, int mode,
-                        int passes, const double* xsep, hipStream_t s, const KTime* tm) {
+                        int passes, const double* xsep, hipStream_t s, const KTime* tm,
+                        const DevTables* halves) {
     if (N == 0) return hipSuccess;
     switch (mode) {
-        case TDS_F64: go_sweep<double, double, kSweep64>(t, F, X, N, passes, xsep, s, tm); break;
-        case TDS_F32_WIDE: go_sweep<float, double, kSweep64>(t, F, X, N, passes, xsep, s, tm); break;
-        case TDS_F32: go_sweep<float, float, kSweep32>(t, F, X, N, passes, xsep, s, tm); break;
+        case TDS_F64:
+            go_sweep<double, double, kSweep64>(t, F, X, N, passes, xsep, s, tm, nullptr);
+            break;
+        case TDS_F32_WIDE:
+            go_sweep<float, double, kSweep64>(t, F, X, N, passes, xsep, s, tm, nullptr);
+            break;
+        case TDS_F32:
+            go_sweep<float, float, kSweep32>(t, F, X, N, passes, xsep, s, tm, nullptr);
+            break;
         case TDS_F32_REFINED:
-            go_sweep<float, double, kSweepRefined>(t, F, X, N, passes, xsep, s, tm);
+            go_sweep<float, double, kSweepRefined>(t, F, X, N, passes, xsep, s, tm, halves);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -999,8 +1128,12 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
 
 template <int TM>
 static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, int passes,
-                        hipStream_t s, const KTime* tm) {
+                        bool halves, hipStream_t s, const KTime* tm) {
     const dim3 g((unsigned)items);
+    if (TM == 64 && halves && mode == TDS_F32_REFINED) {
+        launch_k(k_sweep_batch_halves, g, dim3(2 * kWG), 0, s, tm, D, K, passes);
+        return;
+    }
     switch (mode) {
         case TDS_F64:
             launch_k(k_sweep_batch<TM, double, double, kSweep64>, g, dim3(kWG), 0, s, tm,
@@ -1022,7 +1155,8 @@ static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, 
 }
 
 hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t scans,
-                        int32_t bucket, int mode, int passes, const KTime* tm, hipStream_t s) {
+                        int32_t bucket, int mode, int passes, bool halves, const KTime* tm,
+                        hipStream_t s) {
     if (items == 0) return hipSuccess;
     if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
     if (items > INT32_MAX) return hipErrorInvalidValue;
@@ -1048,9 +1182,9 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
         if (e != hipSuccess) return e;
     }
     if (bucket == 32)
-        batch_sweep<32>(D, K, items, mode, passes, s, tm ? tm + 2 : nullptr);
+        batch_sweep<32>(D, K, items, mode, passes, false, s, tm ? tm + 2 : nullptr);
     else
-        batch_sweep<64>(D, K, items, mode, passes, s, tm ? tm + 2 : nullptr);
+        batch_sweep<64>(D, K, items, mode, passes, halves, s, tm ? tm + 2 : nullptr);
     return hipGetLastError();
 }
 

@@ -47,7 +47,43 @@ int32_t default_blocks(int64_t M) {
 // Block-restarted elimination of every block's interior rows and the
 // block's responses u, v to its left / right interface value (Lemma 1), for
 // the matrix with sub-diagonal lo (A[i+1][i] = lo[i]), diagonal o.b64 and
-// super-diagonal up (A[i][i+1] = up[i]).
+// super-diagonal up (A[i][i+1] = up[i]).  The recurrences run in the host's
+// extended precision (long double) and the tables are rounded to FP64 once:
+// on a nearly singular A (the Poisson matrix) the sweeps multiply the
+// boundary values, which are much larger than the right-hand side, by u and
+// v, so the tables' own rounding shows directly in the residual.
+using wide = long double;
+
+// one block's elimination factors and responses; cp, rd, u, v: i1 - i0 + 1
+// entries each (false: a zero or non-finite pivot)
+static bool block_responses(const double* lo, const double* b, const double* up, int64_t i0,
+                            int64_t i1, double cl, double cr, wide* cp, wide* rd, wide* u,
+                            wide* v) {
+    const int64_t n = i1 - i0 + 1;
+    wide cprev = 0.0L;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t i = i0 + k;
+        const wide den = (wide)b[i] - (k > 0 ? (wide)lo[i - 1] * cprev : 0.0L);
+        if (den == 0.0L || bad((double)den)) return false;
+        rd[k] = 1.0L / den;
+        cp[k] = (k < n - 1) ? (wide)up[i] / den : 0.0L;
+        cprev = cp[k];
+    }
+    // u = T^{-1}(-cl e_first): forward elimination then back substitution
+    wide d = -(wide)cl * rd[0];
+    u[0] = d;
+    for (int64_t k = 1; k < n; ++k) {
+        d = (0.0L - (wide)lo[i0 + k - 1] * d) * rd[k];
+        u[k] = d;
+    }
+    for (int64_t k = n - 2; k >= 0; --k) u[k] -= cp[k] * u[k + 1];
+    // v = T^{-1}(-cr e_last): only the last row is non-zero after the
+    // forward elimination
+    v[n - 1] = -(wide)cr * rd[n - 1];
+    for (int64_t k = n - 2; k >= 0; --k) v[k] = -cp[k] * v[k + 1];
+    return true;
+}
+
 static int block_tables(HostTables& o, const double* lo, const double* up) {
     const int64_t M = o.M;
     const int32_t P = o.P;
@@ -57,31 +93,25 @@ static int block_tables(HostTables& o, const double* lo, const double* up) {
     o.rd64.assign(M, 0.0);
     o.u.assign(M, 0.0);
     o.v.assign(M, 0.0);
+    std::vector<wide> cp, rd, u, v;
     for (int32_t j = 0; j < P; ++j) {
         const int64_t i0 = (j == 0) ? s[0] : s[j] + 1;
         const int64_t i1 = s[j + 1] - 1;
-        double cprev = 0.0;
-        for (int64_t i = i0; i <= i1; ++i) {
-            double den = b[i] - (i > i0 ? lo[i - 1] * cprev : 0.0);
-            if (den == 0.0 || bad(den)) return TDS_ESINGULAR;
-            o.rd64[i] = 1.0 / den;
-            o.cp64[i] = (i < i1) ? up[i] / den : 0.0;
-            cprev = o.cp64[i];
-        }
+        const int64_t n = i1 - i0 + 1;
+        cp.resize(n);
+        rd.resize(n);
+        u.resize(n);
+        v.resize(n);
         const double cl = (j > 0) ? lo[i0 - 1] : 0.0;     // A[i0][i0-1]
         const double cr = (j < P - 1) ? up[i1] : 0.0;     // A[i1][i1+1]
-        // u = T^{-1}(-cl e_first): forward elimination then back substitution
-        double d = -cl * o.rd64[i0];
-        o.u[i0] = d;
-        for (int64_t i = i0 + 1; i <= i1; ++i) {
-            d = (0.0 - lo[i - 1] * d) * o.rd64[i];
-            o.u[i] = d;
+        if (!block_responses(lo, b, up, i0, i1, cl, cr, cp.data(), rd.data(), u.data(), v.data()))
+            return TDS_ESINGULAR;
+        for (int64_t k = 0; k < n; ++k) {
+            o.cp64[i0 + k] = (double)cp[k];
+            o.rd64[i0 + k] = (double)rd[k];
+            o.u[i0 + k] = (double)u[k];
+            o.v[i0 + k] = (double)v[k];
         }
-        for (int64_t i = i1 - 1; i >= i0; --i) o.u[i] -= o.cp64[i] * o.u[i + 1];
-        // v = T^{-1}(-cr e_last): only the last row is non-zero after the
-        // forward elimination
-        o.v[i1] = -cr * o.rd64[i1];
-        for (int64_t i = i1 - 1; i >= i0; --i) o.v[i] = -o.cp64[i] * o.v[i + 1];
     }
     return TDS_OK;
 }
@@ -262,6 +292,77 @@ int host_prepare_general(const double* lo, const double* diag, const double* up,
     }
     o.general = 1;
     return block_tables(o, o.l64.data(), o.a64.data());
+}
+
+// Half-block partition for the refined sweep.  Block j's interior rows
+// i0..i1 become the left half i0..m-1 (`lead` rows), the middle row
+// m = i0 + lead and the right half m+1..i1; as segments of a partition of
+// 2P blocks, the left half's interface row is s_j and the right half's is m,
+// so block_tables gives each half its zero-boundary elimination and its
+// responses u, v to the values at its two ends (Lemma 1 per half).  With x
+// at the middle row written through the halves,
+//     x_{m-1} = x0_{m-1} + x(s_j) u_{m-1} + x_m v_{m-1},
+//     x_{m+1} = x0_{m+1} + x_m u_{m+1} + x(s_{j+1}) v_{m+1},
+// row m's equation A[m][m-1] x_{m-1} + b_m x_m + A[m][m+1] x_{m+1} = f_m
+// gives x_m with the factor 1 / (b_m + A[m][m-1] v_{m-1} + A[m][m+1] u_{m+1}),
+// kept in mid_inv[2j+1].
+int half_tables(const HostTables& o, int32_t lead, HostTables& h) {
+    const int64_t M = o.M;
+    const int32_t P = o.P;
+    if (lead < 1 || (int64_t)P * 2 > (int64_t)1 << 30) return TDS_EUNSUPPORTED;
+    h = HostTables();
+    h.M = M;
+    h.P = 2 * P;
+    h.general = o.general;
+    h.starts.assign(2 * (size_t)P + 1, 0);
+    h.max_rows = 0;
+    for (int32_t j = 0; j < P; ++j) {
+        const int64_t i0 = (j == 0) ? o.starts[0] : o.starts[j] + 1;
+        const int64_t cnt = o.starts[j + 1] - i0;
+        if (cnt < lead + 2 || cnt > 2 * (int64_t)lead + 1) return TDS_EUNSUPPORTED;
+        h.starts[2 * j] = o.starts[j];
+        h.starts[2 * j + 1] = i0 + lead;
+    }
+    h.starts[2 * (size_t)P] = M;
+    for (int32_t k = 0; k < h.P; ++k)
+        h.max_rows = (int32_t)std::max<int64_t>(h.max_rows, h.starts[k + 1] - h.starts[k]);
+    h.a64 = o.a64;
+    h.l64 = o.l64;
+    h.b64 = o.b64;
+    h.rho.assign(h.P, 0.0);
+    h.lam.assign(h.P, 0.0);
+    int rc = block_tables(h, h.l64.data(), h.a64.data());
+    if (rc) return rc;
+    // the Schur complement b_m + A[m][m-1] v_{m-1} + A[m][m+1] u_{m+1} cancels
+    // (1/16 of its terms on the Poisson matrix): it is formed from the
+    // halves' extended-precision responses, not from their FP64 tables
+    h.mid_inv.assign(h.P, 0.0);
+    std::vector<wide> cp, rd, u, v;
+    for (int32_t j = 0; j < P; ++j) {
+        const int64_t m = h.starts[2 * j + 1];
+        const int64_t a0 = (j == 0) ? h.starts[0] : h.starts[2 * j] + 1;   // left half a0..m-1
+        const int64_t b1 = h.starts[2 * j + 2] - 1;                          // right half m+1..b1
+        const int64_t n = std::max<int64_t>(m - a0, b1 - m);
+        cp.resize(n);
+        rd.resize(n);
+        u.resize(n);
+        v.resize(n);
+        const double* lo = h.l64.data();
+        const double* up = h.a64.data();
+        const double* bb = h.b64.data();
+        if (!block_responses(lo, bb, up, a0, m - 1, j > 0 ? lo[a0 - 1] : 0.0, up[m - 1], cp.data(),
+                             rd.data(), u.data(), v.data()))
+            return TDS_ESINGULAR;
+        const wide vA = v[m - 1 - a0];
+        if (!block_responses(lo, bb, up, m + 1, b1, lo[m], j < P - 1 ? up[b1] : 0.0, cp.data(),
+                             rd.data(), u.data(), v.data()))
+            return TDS_ESINGULAR;
+        const wide uB = u[0];
+        const wide den = (wide)bb[m] + (wide)lo[m - 1] * vA + (wide)up[m] * uB;
+        if (den == 0.0L || bad((double)den)) return TDS_ESINGULAR;
+        h.mid_inv[2 * j + 1] = (double)(1.0L / den);
+    }
+    return TDS_OK;
 }
 
 // Theorem 2 (eq. theor_2) written out as one coefficient matrix: for the
