@@ -150,6 +150,73 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
     }
 }
 
+// beta_item with four right-hand sides per lane (FP32 input, N a multiple
+// of 4, F 16-byte aligned): each row access of a wavefront is one 1 KB span
+// read by 16-byte loads, a quarter of the load instructions.  Per
+// right-hand side the arithmetic is beta_item's (the same rows per
+// wavefront in the same order, the same reduction), so the weights are
+// bitwise the same.  Item (tile, j): block j x 256 right-hand sides.
+constexpr int kBeta4Rhs = 4 * kBetaRhs;
+
+template <int TMAX>
+__device__ __forceinline__ void beta_item4(const DevTables& T, const float* __restrict__ F,
+                                           int64_t N, int32_t j, int64_t tile,
+                                           double* __restrict__ betaR,
+                                           double* __restrict__ betaL,
+                                           double2* __restrict__ red) {
+    constexpr int TQ = TMAX / kBetaWaves;
+    const int64_t n0 = tile * kBeta4Rhs;
+    if (n0 >= N) return;                                  // uniform per workgroup
+    const int64_t lo = cst(T.starts)[j];
+    const int t = (int)(cst(T.starts)[j + 1] - lo);
+    const int lane = threadIdx.x % kBetaRhs;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kBetaRhs);
+    const bool live = n0 + 4 * lane < N;
+    // lanes past N read the last group of four columns and store nothing
+    const uint32_t off = (uint32_t)(live ? 4 * lane : N - 4 - n0) * sizeof(float);
+    const float* fb = F + lo * N + n0;
+    const int r0 = wv * TQ;
+    const cptr<double2> w = cst(T.wpad + (int64_t)j * TMAX + r0);
+    float4 v[TQ];
+#pragma unroll
+    for (int r = 0; r < TQ; ++r) {
+        const int row = r0 + r < t ? r0 + r : t - 1;
+        v[r] = at_off((const float4*)(fb + (int64_t)row * N), off);
+    }
+    double bR[4] = {0.0, 0.0, 0.0, 0.0}, bL[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < TQ; ++r) {
+        const double cR = w[r].x, cL = w[r].y;
+        const float e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bR[q] = fma(cR, (double)e[q], bR[q]);
+            bL[q] = fma(cL, (double)e[q], bL[q]);
+        }
+    }
+    if (wv > 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            red[((wv - 1) * 4 + q) * kBetaRhs + lane] = make_double2(bR[q], bL[q]);
+    __syncthreads();
+    if (wv == 0 && live) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < kBetaWaves - 1; ++k) {
+                const double2 p = red[(k * 4 + q) * kBetaRhs + lane];
+                bR[q] += p.x;
+                bL[q] += p.y;
+            }
+        if (j < T.P - 1)
+            *(double4*)&betaR[(int64_t)j * N + n0 + 4 * lane] =
+                make_double4(bR[0], bR[1], bR[2], bR[3]);
+        if (j > 0)
+            *(double4*)&betaL[(int64_t)j * N + n0 + 4 * lane] =
+                make_double4(bL[0], bL[1], bL[2], bL[3]);
+    }
+}
+
 // Batch beta weights: one workgroup per item (block j x 256 right-hand
 // sides), each wavefront 64 right-hand sides and every row of the block.
 // The batch's blocks are short (<= TMAX = 32 or 64 rows), so beta_item's
@@ -735,6 +802,14 @@ constexpr int sweep_min_waves() {
 
 // ==========================================================================
 // single-matrix kernels: grid (RHS tiles, blocks)
+template <int TMAX>
+__global__ __launch_bounds__(kWG) void k_beta4(DevTables T, const float* __restrict__ F, int64_t N,
+                                               double* __restrict__ betaR,
+                                               double* __restrict__ betaL) {
+    __shared__ double2 red[(kBetaWaves - 1) * 4 * kBetaRhs];
+    beta_item4<TMAX>(T, F, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, betaR, betaL, red);
+}
+
 template <int TMAX, typename Fin>
 __global__ __launch_bounds__(kWG) void k_beta(DevTables T, const Fin* __restrict__ F, int64_t N,
                                               double* __restrict__ betaR,
@@ -980,6 +1055,18 @@ int32_t rows_bucket(int32_t max_rows) {
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
                        double* betaL, hipStream_t s, const KTime* tm) {
     if (t.P < 2 || N == 0) return hipSuccess;
+    // FP32 input in rows of whole 16-byte groups: four right-hand sides per lane
+    if (f32 && N % 4 == 0 && ((uintptr_t)F & 15) == 0 &&
+        (t.wpad_rows == 32 || t.wpad_rows == 64 || t.wpad_rows == 128)) {
+        const dim3 g4((unsigned)((N + kBeta4Rhs - 1) / kBeta4Rhs), (unsigned)t.P, 1);
+        if (t.wpad_rows == 32)
+            launch_k(k_beta4<32>, g4, dim3(kWG), 0, s, tm, t, (const float*)F, N, betaR, betaL);
+        else if (t.wpad_rows == 64)
+            launch_k(k_beta4<64>, g4, dim3(kWG), 0, s, tm, t, (const float*)F, N, betaR, betaL);
+        else
+            launch_k(k_beta4<128>, g4, dim3(kWG), 0, s, tm, t, (const float*)F, N, betaR, betaL);
+        return hipGetLastError();
+    }
     const dim3 g((unsigned)((N + kBetaRhs - 1) / kBetaRhs), (unsigned)t.P, 1);
 #define TDS_BETA(TM, FT) \
     launch_k(k_beta<TM, FT>, g, dim3(kWG), 0, s, tm, t, (const FT*)F, N, betaR, betaL)
