@@ -12,14 +12,17 @@
 // occupying VGPRs.  (Reading them as constant memory also keeps them scalar
 // when their pointers come from a descriptor table, as in the batch.)
 //
-//   beta   eq. beta_symn: beta^R_j, beta^L_j of block j (FP64 accumulation).
+//   beta   eq. beta_symn: beta^R_j, beta^L_j of block j (FP64 accumulation;
+//          FP32 series with N % 4 == 0 read four right-hand sides per lane).
 //   iface  Theorem 2 (eq. theor_2): x at the interface rows, in one of three
 //          orders: the two first-order recurrences S^R_{k+1} = rho_k S^R_k +
 //          beta^R_k and S^L_k = beta^L_k + lam_k S^L_{k+1}, x(s_k) = S^R_k +
 //          S^L_k (default); Algorithm 4's dichotomy, level by level; or the
 //          double sum itself as one dense product on the FP64 matrix cores.
 //   sweep  Lemma 1 / Algorithm 1 step 3: the sweep inside each block with
-//          both boundary values known; X leaves with streaming stores.
+//          both boundary values known; X leaves with streaming stores.  The
+//          refined sweep of 35..64-row blocks takes each block in two
+//          halves on separate wavefronts, joined at the middle row.
 //
 // Each step is a device function over one work item; the single-matrix
 // kernels index items by their 2-D grid, the batch kernels (many matrices of
