@@ -323,12 +323,6 @@ int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hi
     return TDS_OK;
 }
 
-__global__ void k_cast_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = i; k < n; k += stride) dst[k] = (float)src[k];
-}
-
 // zero fill by a kernel (not a memset node, so that captured graphs replay it
 // reliably)
 __global__ void k_zero_f64(double* __restrict__ dst, int64_t n) {
@@ -461,22 +455,16 @@ int tdsolve_backward(tds_handle h, const void* X, const void* gX, void* gF, doub
         return TDS_OK;
     }
     // X, gX are double, F (hence gF) is float: solve in FP64 into a private
-    // FP64 buffer, reduce from it, then round into gF.
+    // FP64 buffer, reduce from it and round it into gF in the same pass.
     const size_t gbytes = align256(sizeof(double) * (size_t)t.M * (size_t)N);
     void* g64 = nullptr;
     hipError_t e = hipMallocAsync(&g64, gbytes, s);
     if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
     if (e != hipSuccess) return TDS_EHIP;
     rc = series_impl(h, gX, g64, N, TDS_F64, s, TDS_F64);
-    if (!rc && launch_adjoint_reduce(t, X, g64, false, false, N, nullptr, ga, gb, s) != hipSuccess)
+    if (!rc && launch_adjoint_reduce(t, X, g64, false, false, N, (float*)gF, ga, gb, s) !=
+                   hipSuccess)
         rc = TDS_EHIP;
-    if (!rc) {
-        const int64_t n = t.M * N;
-        unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_cast_f32, dim3(blocks), dim3(256), 0, s, (const double*)g64,
-                           (float*)gF, n);
-        if (hipGetLastError() != hipSuccess) rc = TDS_EHIP;
-    }
     if (hipFreeAsync(g64, s) != hipSuccess && !rc) rc = TDS_EHIP;
     return rc;
 }

@@ -69,11 +69,13 @@ __global__ __launch_bounds__(kWG) void k_resid_finish(const double* __restrict__
 // --------------------------------------------------------------------------
 // Adjoint reductions over the series: one workgroup per row i, a fixed
 // strided order per lane and a fixed LDS tree, so results are bitwise
-// reproducible (no floating-point atomics).
+// reproducible (no floating-point atomics).  g32 (may be null) receives
+// row i of gF rounded to FP32 on the way.
 template <typename Xin, typename Gin>
 __global__ __launch_bounds__(kWG) void k_adjoint_reduce(const Xin* __restrict__ X,
                                                         const Gin* __restrict__ gF, int64_t N,
-                                                        int64_t M, double* __restrict__ ga,
+                                                        int64_t M, float* __restrict__ g32,
+                                                        double* __restrict__ ga,
                                                         double* __restrict__ gb) {
     __shared__ double sa[kWG], sb[kWG];
     const int64_t i = blockIdx.x;
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(kWG) void k_adjoint_reduce(const Xin* __restrict__ 
     for (int64_t n = threadIdx.x; n < N; n += kWG) {
         const double x = (double)X[i * N + n];
         const double g = (double)gF[i * N + n];
+        if (g32) g32[i * N + n] = (float)g;
         accb = fma(g, x, accb);
         if (has_next) {
             const double x1 = (double)X[(i + 1) * N + n];
@@ -135,22 +138,22 @@ hipError_t launch_residual(const DevTables& t, const void* F, const void* X, int
 }
 
 hipError_t launch_adjoint_reduce(const DevTables& t, const void* X, const void* gF, bool f32x,
-                                 bool f32g, int64_t N, double* /*part*/, double* ga,
-                                 double* gb, hipStream_t s) {
-    if (N == 0 || (!ga && !gb)) return hipSuccess;
+                                 bool f32g, int64_t N, float* g32, double* ga, double* gb,
+                                 hipStream_t s) {
+    if (N == 0 || (!ga && !gb && !g32)) return hipSuccess;
     dim3 g((unsigned)t.M, 1, 1);
     if (!f32x && !f32g)
         hipLaunchKernelGGL((k_adjoint_reduce<double, double>), g, dim3(kWG), 0, s,
-                           (const double*)X, (const double*)gF, N, t.M, ga, gb);
+                           (const double*)X, (const double*)gF, N, t.M, g32, ga, gb);
     else if (!f32x && f32g)
         hipLaunchKernelGGL((k_adjoint_reduce<double, float>), g, dim3(kWG), 0, s,
-                           (const double*)X, (const float*)gF, N, t.M, ga, gb);
+                           (const double*)X, (const float*)gF, N, t.M, g32, ga, gb);
     else if (f32x && f32g)
         hipLaunchKernelGGL((k_adjoint_reduce<float, float>), g, dim3(kWG), 0, s,
-                           (const float*)X, (const float*)gF, N, t.M, ga, gb);
+                           (const float*)X, (const float*)gF, N, t.M, g32, ga, gb);
     else
         hipLaunchKernelGGL((k_adjoint_reduce<float, double>), g, dim3(kWG), 0, s,
-                           (const float*)X, (const double*)gF, N, t.M, ga, gb);
+                           (const float*)X, (const double*)gF, N, t.M, g32, ga, gb);
     return hipGetLastError();
 }
 

@@ -180,9 +180,11 @@ hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipS
 hipError_t launch_residual(const DevTables& t, const void* F, const void* X,
                            int64_t N, int mode, double normA, double* part,
                            double* out, hipStream_t s);
+// gb_i, ga_i of the adjoint from X and gF; g32 (may be null): FP32 copy of
+// gF written on the way
 hipError_t launch_adjoint_reduce(const DevTables& t, const void* X,
                                  const void* gF, bool f32x, bool f32g,
-                                 int64_t N, double* part, double* ga,
+                                 int64_t N, float* g32, double* ga,
                                  double* gb, hipStream_t s);
 
 // Rows of partial sums used by the residual and adjoint reductions.
