@@ -859,10 +859,12 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 constexpr int kHalfRhs = 128;        // right-hand sides per workgroup (single matrix)
 
 // one work item of the halves sweep: block j of H's method partition (H.P / 2
-// blocks) x RHS right-hand sides from tile * RHS, on 2 RHS threads; s_f:
-// kHalfRows x 2 RHS floats, s_q: 2 RHS doubles of LDS
-template <int RHS, bool GEN>
-__device__ __forceinline__ void halves_item(const DevTables& H, const float* __restrict__ F,
+// blocks) x RHS right-hand sides from tile * RHS, on 2 RHS threads.  KIND:
+// kSweepRefined (FP32 input, refined_solve; s_f: kHalfRows x 2 RHS floats of
+// LDS) or kSweep64 (FP64 arithmetic on FP32 or FP64 input, no refinement;
+// s_f unused).  s_q: 2 RHS doubles of LDS.
+template <int RHS, typename Fin, int KIND, bool GEN>
+__device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __restrict__ F,
                                             double* __restrict__ X, int64_t N, int32_t j,
                                             int64_t tile, const double* __restrict__ xsep,
                                             int passes, float* s_f, double* s_q) {
@@ -882,18 +884,33 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const float* __r
     double xo = 0.0;
     if (h == 0 && j > 0) xo = xsep[(int64_t)(j - 1) * N + n0 + lane];
     if (h == 1 && j < P - 1) xo = xsep[(int64_t)j * N + n0 + lane];
-    float f[TM];
-    sweep_load<TM, float>(F + i0 * N + n0, lane, N, cnt, f);
-    float fm = 0.0f;
-    if (h == 0) fm = (F + seg_hi * N + n0)[lane];     // row m
-    float* my_f = s_f + threadIdx.x;
-#pragma unroll
-    for (int r = 0; r < TM; ++r) my_f[r * NT] = f[r];
+    Fin f[TM];
+    sweep_load<TM, Fin>(F + i0 * N + n0, lane, N, cnt, f);
+    double fm = 0.0;
+    if (h == 0) fm = (double)(F + seg_hi * N + n0)[lane];     // row m
     double x[TM];
-    refined_solve<TM, GEN, NT>(H, i0, my_f, passes, x);
+    if constexpr (KIND == kSweepRefined) {
+        float* my_f = s_f + threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < TM; ++r) my_f[r * NT] = f[r];
+        refined_solve<TM, GEN, NT>(H, i0, my_f, passes, x);
+    } else {
+        // zero-boundary FP64 sweep of the half; rows past cnt come after the
+        // last real row, whose elimination factor is zero
+        const cptr<double> l64 = cst((GEN ? H.l64 : H.a64) + i0);
+        const cptr<double> cp64 = cst(H.cp64 + i0), rd64 = cst(H.rd64 + i0);
+#pragma unroll
+        for (int r = 0; r < TM; ++r) {
+            const double prev = (r > 0) ? x[r - 1] : 0.0;
+            const double sub = (r > 0) ? l64[r - 1] : 0.0;
+            x[r] = ((double)f[r] - sub * prev) * rd64[r];
+        }
+#pragma unroll
+        for (int r = TM - 2; r >= 0; --r) x[r] -= cp64[r] * x[r + 1];
+    }
     const cptr<double> uu = cst(H.u + i0), vv = cst(H.v + i0);
     if (h == 0)
-        s_q[c] = (double)fm - cst(GEN ? H.l64 : H.a64)[seg_hi - 1] * fma(xo, uu[TM - 1], x[TM - 1]);
+        s_q[c] = fm - cst(GEN ? H.l64 : H.a64)[seg_hi - 1] * fma(xo, uu[TM - 1], x[TM - 1]);
     else
         s_q[RHS + c] = fma(xo, vv[0], x[0]);
     __syncthreads();
@@ -911,16 +928,16 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const float* __r
     }
 }
 
-template <int RHS, bool GEN>
+template <int RHS, typename Fin, int KIND, bool GEN>
 __global__ __launch_bounds__(2 * RHS, 4) void k_sweep_halves(DevTables H,
-                                                             const float* __restrict__ F,
+                                                             const Fin* __restrict__ F,
                                                              double* __restrict__ X, int64_t N,
                                                              const double* __restrict__ xsep,
                                                              int passes) {
-    __shared__ float s_f[kHalfRows * 2 * RHS];
+    __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * RHS : 1];
     __shared__ double s_q[2 * RHS];
-    halves_item<RHS, GEN>(H, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, xsep, passes,
-                          s_f, s_q);
+    halves_item<RHS, Fin, KIND, GEN>(H, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, xsep,
+                                     passes, s_f, s_q);
 }
 
 template <typename Fin, typename Xout, int KIND, bool GEN>
@@ -1017,12 +1034,13 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
                                       s_f);
 }
 
-// the batch's refined sweep when every matrix takes its blocks in halves
-// (BatchDesc::H): one workgroup of 2 x 256 threads per item, the item
-// structure of k_sweep_batch
+// the batch's refined or FP64-arithmetic sweep when every matrix takes its
+// blocks in halves (BatchDesc::H): one workgroup of 2 x 256 threads per item,
+// the item structure of k_sweep_batch
+template <typename Fin, int KIND>
 __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDesc* __restrict__ D,
                                                                    int32_t K, int passes) {
-    __shared__ float s_f[kHalfRows * 2 * kWG];
+    __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * kWG : 1];
     __shared__ double s_q[2 * kWG];
     const int64_t item = xcd_item();
     const int32_t k = find_desc(D, K, item, false);
@@ -1030,8 +1048,9 @@ __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDe
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
     if (local >= (int64_t)d.T.P * tiles) return;        // uniform per workgroup
-    halves_item<kWG, false>(d.H, (const float*)d.F, (double*)d.X, d.N, (int32_t)(local / tiles),
-                            local % tiles, d.xsep, passes, s_f, s_q);
+    halves_item<kWG, Fin, KIND, false>(d.H, (const Fin*)d.F, (double*)d.X, d.N,
+                                       (int32_t)(local / tiles), local % tiles, d.xsep, passes,
+                                       s_f, s_q);
 }
 
 // ==========================================================================
@@ -1154,11 +1173,11 @@ static void go_sweep_t(const DevTables& t, const void* F, void* X, int64_t N, in
                        const DevTables* halves) {
     const int m = t.max_rows;
     const dim3 g = grid2(N, t.P);
-    if constexpr (KIND == kSweepRefined) {
+    if constexpr (KIND == kSweepRefined || (KIND == kSweep64 && std::is_same<Xout, double>::value)) {
         if (halves && m > kHalfRows && m <= 2 * kHalfRows && halves->P == 2 * t.P) {
-            launch_k(k_sweep_halves<kHalfRhs, GEN>,
+            launch_k(k_sweep_halves<kHalfRhs, Fin, KIND, GEN>,
                      dim3((unsigned)((N + kHalfRhs - 1) / kHalfRhs), t.P, 1), dim3(2 * kHalfRhs),
-                     0, s, tm, *halves, (const float*)F, (double*)X, N, xsep, passes);
+                     0, s, tm, *halves, (const Fin*)F, (double*)X, N, xsep, passes);
             return;
         }
     }
@@ -1200,10 +1219,10 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
     if (N == 0) return hipSuccess;
     switch (mode) {
         case TDS_F64:
-            go_sweep<double, double, kSweep64>(t, F, X, N, passes, xsep, s, tm, nullptr);
+            go_sweep<double, double, kSweep64>(t, F, X, N, passes, xsep, s, tm, halves);
             break;
         case TDS_F32_WIDE:
-            go_sweep<float, double, kSweep64>(t, F, X, N, passes, xsep, s, tm, nullptr);
+            go_sweep<float, double, kSweep64>(t, F, X, N, passes, xsep, s, tm, halves);
             break;
         case TDS_F32:
             go_sweep<float, float, kSweep32>(t, F, X, N, passes, xsep, s, tm, nullptr);
@@ -1220,8 +1239,16 @@ template <int TM>
 static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, int passes,
                         bool halves, hipStream_t s, const KTime* tm) {
     const dim3 g((unsigned)items);
-    if (TM == 64 && halves && mode == TDS_F32_REFINED) {
-        launch_k(k_sweep_batch_halves, g, dim3(2 * kWG), 0, s, tm, D, K, passes);
+    if (TM == 64 && halves && mode != TDS_F32) {
+        if (mode == TDS_F32_REFINED)
+            launch_k(k_sweep_batch_halves<float, kSweepRefined>, g, dim3(2 * kWG), 0, s, tm, D, K,
+                     passes);
+        else if (mode == TDS_F64)
+            launch_k(k_sweep_batch_halves<double, kSweep64>, g, dim3(2 * kWG), 0, s, tm, D, K,
+                     passes);
+        else
+            launch_k(k_sweep_batch_halves<float, kSweep64>, g, dim3(2 * kWG), 0, s, tm, D, K,
+                     passes);
         return;
     }
     switch (mode) {

@@ -72,14 +72,19 @@ def test_batch_ragged_shapes_and_empty_series():
         _check(a_l[k], b_l[k], F_l[k].astype(np.float64), Xs[k].cpu().numpy(), P)
 
 
-def test_batch_matches_single_plans_bitwise():
+@pytest.mark.parametrize("mode", ["f32_refined", "f64", "f32_wide"])
+def test_batch_matches_single_plans_bitwise(mode):
+    # 64-row blocks that every matrix's halves fit: the batch and the single
+    # plans take the same sweep
     w = wl.uneven_batch(seed=11, K=6, M_lo=128, M_hi=1500, N_hi=400)
     items = w["items"]
     bp = t.BatchPlan([it["a"] for it in items], [it["b"] for it in items])
     Fs = [torch.from_numpy(it["F"]).to(DEV) for it in items]
-    Xs = bp.solve(Fs, mode="f32_refined")
+    if mode == "f64":
+        Fs = [F.double() for F in Fs]
+    Xs = bp.solve(Fs, mode=mode)
     for k, it in enumerate(items):
-        X1 = t.Plan(it["a"], it["b"], 0).solve(Fs[k], mode="f32_refined")
+        X1 = t.Plan(it["a"], it["b"], 0).solve(Fs[k], mode=mode)
         assert torch.equal(X1, Xs[k])
 
 

@@ -1,7 +1,7 @@
-"""GPU: the refined sweep of blocks of 34..65 interior rows, which the
-library solves in two halves per block (a left half of 32 rows, the middle
-row from its own equation, a right half of 1..31 rows; Lemma 1 per half),
-against the CPU oracle's sweep.
+"""GPU: the sweep of blocks of 34..65 interior rows in the modes with FP64
+results, which the library solves in two halves per block (a left half of
+32 rows, the middle row from its own equation, a right half of 1..31 rows;
+Lemma 1 per half), against the CPU oracle's sweep.
 
 The shapes cover even and ragged partitions, the shortest right half (one
 row: blocks of 35 rows), one block (no interface rows), column counts that
@@ -50,8 +50,9 @@ def _r2(a, b, F, X):
     (64 * 30 - 7, 257, 30, 1),  # 64 and 63 rows; one live column in the last workgroup
     (680, 70, 20, 0),      # 34-row segments: below the split, swept whole
 ])
-def test_refined_halves_match_oracle(M, N, P, halves):
-    print(f"halves M={M} N={N} P={P}", flush=True)
+@pytest.mark.parametrize("mode", ["f32_refined", "f64", "f32_wide"])
+def test_halves_match_oracle(M, N, P, halves, mode):
+    print(f"halves M={M} N={N} P={P} mode={mode}", flush=True)
     rng = np.random.default_rng(M + N + P)
     a = rng.uniform(-1, -0.2, size=M - 1)
     b = np.concatenate([[0], np.abs(a)]) + np.concatenate([np.abs(a), [0]]) + rng.uniform(0.05, 0.5, size=M)
@@ -60,7 +61,8 @@ def test_refined_halves_match_oracle(M, N, P, halves):
     ref = oracle.thomas(a, b, F)
     plan = t.Plan(a, b, P)
     assert plan.P == P and plan.info().refined_halves == halves
-    X = plan.solve(torch.from_numpy(F32).to(DEV), mode="f32_refined").cpu().numpy()
+    Fd = torch.from_numpy(F32).to(DEV)
+    X = plan.solve(Fd.double() if mode == "f64" else Fd, mode=mode).cpu().numpy()
     e = np.max(np.abs(X - ref), axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
     tol = _tol(a, b, F, ref, P)
     bad = np.nonzero(e > tol)[0]
