@@ -837,8 +837,12 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     // lanes per block row, conflict-free) so that its VGPRs hold only x and
     // the FP32 elimination values
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
-    sweep_item<TMAX, Fin, Xout, KIND, GEN>(T, F, X, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, xsep,
-                                      passes, s_f);
+    // FP32 input: the blocks in reverse, so the rows the beta pass read last
+    // are swept first (its 16-byte-load tiles are this kernel's 256 RHS, so
+    // each tile already runs on the XCD that read it; see k_sweep_halves)
+    const int32_t j = std::is_same<Fin, float>::value ? (int32_t)(gridDim.y - 1 - blockIdx.y)
+                                                      : (int32_t)blockIdx.y;
+    sweep_item<TMAX, Fin, Xout, KIND, GEN>(T, F, X, N, j, (int64_t)blockIdx.x, xsep, passes, s_f);
 }
 
 // Refined sweep of a block in two halves (tables from half_tables): block
