@@ -40,8 +40,8 @@ struct tds_plan {
     std::vector<DevTables> devs;
     std::vector<DevTables> devs_h;       // half-block tables, when every matrix has them
     std::vector<BatchDesc> desc;         // last descriptors uploaded
-    BatchDesc* d_desc = nullptr;
-    size_t desc_cap = 0;
+    BatchDesc* d_desc = nullptr;         // descriptors, then the item owner maps
+    size_t desc_bytes = 0;               // capacity of d_desc
     // the last series call, for tdsolve_status
     bool have_last = false;
     int32_t last_mode = 0, last_passes = 0;
@@ -736,31 +736,56 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     // descriptors go to the device only when they change, so that repeated
     // calls on the same buffers (e.g. replays of a captured graph) carry no
     // host-to-device copy
+    // Behind the descriptors: the matrix of every beta-and-sweep item and of
+    // every interface item, so that a workgroup finds its matrix by one load.
+    const size_t dbytes = align256(sizeof(BatchDesc) * desc.size());
+    const size_t ibytes = align256(sizeof(int32_t) * (size_t)items);
+    const size_t total = dbytes + ibytes + sizeof(int32_t) * (size_t)std::max<int64_t>(scans, 1);
     const bool same = desc.size() == h->desc.size() &&
                       memcmp(desc.data(), h->desc.data(), sizeof(BatchDesc) * desc.size()) == 0;
     if (!same) {
-        if (h->desc_cap < desc.size()) {
+        std::vector<unsigned char> img;
+        try {
+            img.assign(total, 0);
+        } catch (...) {
+            return TDS_ENOMEM;
+        }
+        memcpy(img.data(), desc.data(), sizeof(BatchDesc) * desc.size());
+        int32_t* oi = (int32_t*)(img.data() + dbytes);
+        int32_t* os = (int32_t*)(img.data() + dbytes + ibytes);
+        for (int32_t k = 0; k < K; ++k) {
+            const BatchDesc& d = desc[k];
+            if (d.N == 0) continue;
+            const int64_t ni = (int64_t)d.T.P * ((d.N + kWG - 1) / kWG);
+            for (int64_t i = 0; i < ni; ++i) oi[d.item0 + i] = k;
+            if (d.T.P > 1) {
+                const int64_t ns = (d.N + ((int64_t)1 << d.lgR) - 1) >> d.lgR;
+                for (int64_t i = 0; i < ns; ++i) os[d.scan0 + i] = k;
+            }
+        }
+        if (h->desc_bytes < total) {
             if (h->d_desc) {
                 if (hipDeviceSynchronize() != hipSuccess) return TDS_EHIP;
                 (void)hipFree(h->d_desc);
                 h->d_desc = nullptr;
+                h->desc_bytes = 0;
             }
-            if (hipMalloc(&h->d_desc, sizeof(BatchDesc) * desc.size()) != hipSuccess)
-                return TDS_ENOMEM;
-            h->desc_cap = desc.size();
+            if (hipMalloc(&h->d_desc, total) != hipSuccess) return TDS_ENOMEM;
+            h->desc_bytes = total;
         }
         // ordered after any queued work that still reads the old descriptors
         if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return TDS_EHIP;
-        if (hipMemcpy(h->d_desc, desc.data(), sizeof(BatchDesc) * desc.size(),
-                      hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(h->d_desc, img.data(), total, hipMemcpyHostToDevice) != hipSuccess)
             return TDS_EHIP;
         h->desc = desc;
     }
+    const int32_t* own_items = (const int32_t*)((const unsigned char*)h->d_desc + dbytes);
+    const int32_t* own_scans = (const int32_t*)((const unsigned char*)h->d_desc + dbytes + ibytes);
     KTime* tm = timing_slot(h);
     if (h->timing && !tm) return TDS_EHIP;
     if (tm && scans == 0) empty_phase(h, 1);
-    if (launch_batch(h->d_desc, K, items, scans, h->bucket, mode, h->passes, h->has_halves, tm,
-                     (hipStream_t)stream) != hipSuccess)
+    if (launch_batch(h->d_desc, own_items, own_scans, items, scans, h->bucket, mode, h->passes,
+                     h->has_halves, tm, (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
     remember(h, F, X, N, K, mode);
     return TDS_OK;

@@ -171,9 +171,12 @@ struct BatchDesc {
 // `tm` (may be null): start/stop events of the beta, interface and sweep
 // launches, in that order (the interface pair stays unrecorded when no
 // matrix has interface rows, scans == 0).
-hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items,
-                        int64_t scans, int32_t bucket, int mode, int passes,
-                        bool halves, const KTime* tm, hipStream_t s);
+// own_items[i] / own_scans[i]: the matrix of beta-and-sweep item i / of
+// interface item i (device arrays of items / scans entries).
+hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items,
+                        const int32_t* own_scans, int64_t items, int64_t scans,
+                        int32_t bucket, int mode, int passes, bool halves,
+                        const KTime* tm, hipStream_t s);
 
 // uniform[-1, 1) values from a counter-based generator (timing inputs)
 hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipStream_t s);

@@ -972,22 +972,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_stream(DevTables T, const Fin* __
 
 // ==========================================================================
 // batch kernels: one 1-D launch per step over the work items of all
-// matrices; item ranges per matrix are prefix sums in the descriptors.
-__device__ __forceinline__ int32_t find_desc(const BatchDesc* __restrict__ D, int32_t K,
-                                             int64_t item, bool scan) {
-    // last k whose first item is <= item (the ranges are in matrix order)
-    int32_t lo = 0, hi = K - 1;
-    const cptr<BatchDesc> d = cst(D);
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        const int64_t first = scan ? d[mid].scan0 : d[mid].item0;
-        if (first <= item)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
+// matrices; item ranges per matrix are prefix sums in the descriptors, and
+// own[item] names the matrix of each item (one scalar load in place of a
+// binary search over the descriptors, whose chain of dependent loads held
+// every workgroup for microseconds before its first load of F).
 
 // Item of a batch workgroup.  Workgroups are dispatched to the chip's 8
 // XCDs (each with its own L2) round-robin by index; consecutive items are
@@ -1012,9 +1000,10 @@ __device__ __forceinline__ int64_t xcd_item() {
 // one workgroup per item: wavefront wv takes right-hand sides wv*64 .. +63
 // of the item's 256 (beta_rows_item)
 template <int TMAX, typename Fin>
-__global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict__ D, int32_t K) {
+__global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict__ D,
+                                                    const int32_t* __restrict__ own) {
     const int64_t item = xcd_item();
-    const int32_t k = find_desc(D, K, item, false);
+    const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
@@ -1028,12 +1017,12 @@ __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict_
 // (G_k R_k <= kScanBatchThreads); LDS for the largest shape, G R = 256 with
 // per <= kScanMaxPerBatch
 __global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
-    const BatchDesc* __restrict__ D, int32_t K) {
+    const BatchDesc* __restrict__ D, const int32_t* __restrict__ own) {
     // carries 2 G R + factors 2 G + S^R by row G per R, with G R <= 256
     __shared__ double S[2 * kScanBatchThreads + 2 * kScanBatchMaxGroups +
                         kScanBatchThreads * kScanMaxPerBatch];
     const int64_t item = xcd_item();
-    const int32_t k = find_desc(D, K, item, true);
+    const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.scan0;
     if (d.T.P < 2 || (local << d.lgR) >= d.N) return;   // uniform per workgroup
@@ -1043,10 +1032,10 @@ __global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
 
 template <int TMAX, typename Fin, typename Xout, int KIND>
 __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_batch(
-    const BatchDesc* __restrict__ D, int32_t K, int passes) {
+    const BatchDesc* __restrict__ D, const int32_t* __restrict__ own, int passes) {
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
     const int64_t item = xcd_item();
-    const int32_t k = find_desc(D, K, item, false);
+    const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
@@ -1061,11 +1050,12 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 // the item structure of k_sweep_batch
 template <typename Fin, int KIND>
 __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDesc* __restrict__ D,
-                                                                   int32_t K, int passes) {
+                                                                   const int32_t* __restrict__ own,
+                                                                   int passes) {
     __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * kWG : 1];
     __shared__ double s_q[2 * kWG];
     const int64_t item = xcd_item();
-    const int32_t k = find_desc(D, K, item, false);
+    const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.item0;
     const int64_t tiles = (d.N + kWG - 1) / kWG;
@@ -1258,44 +1248,44 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
 }
 
 template <int TM>
-static void batch_sweep(const BatchDesc* D, int32_t K, int64_t items, int mode, int passes,
-                        bool halves, hipStream_t s, const KTime* tm) {
+static void batch_sweep(const BatchDesc* D, const int32_t* own, int64_t items, int mode,
+                        int passes, bool halves, hipStream_t s, const KTime* tm) {
     const dim3 g((unsigned)items);
     if (TM == 64 && halves && mode != TDS_F32) {
         if (mode == TDS_F32_REFINED)
-            launch_k(k_sweep_batch_halves<float, kSweepRefined>, g, dim3(2 * kWG), 0, s, tm, D, K,
+            launch_k(k_sweep_batch_halves<float, kSweepRefined>, g, dim3(2 * kWG), 0, s, tm, D, own,
                      passes);
         else if (mode == TDS_F64)
-            launch_k(k_sweep_batch_halves<double, kSweep64>, g, dim3(2 * kWG), 0, s, tm, D, K,
+            launch_k(k_sweep_batch_halves<double, kSweep64>, g, dim3(2 * kWG), 0, s, tm, D, own,
                      passes);
         else
-            launch_k(k_sweep_batch_halves<float, kSweep64>, g, dim3(2 * kWG), 0, s, tm, D, K,
+            launch_k(k_sweep_batch_halves<float, kSweep64>, g, dim3(2 * kWG), 0, s, tm, D, own,
                      passes);
         return;
     }
     switch (mode) {
         case TDS_F64:
             launch_k(k_sweep_batch<TM, double, double, kSweep64>, g, dim3(kWG), 0, s, tm,
-                     D, K, passes);
+                     D, own, passes);
             break;
         case TDS_F32_WIDE:
             launch_k(k_sweep_batch<TM, float, double, kSweep64>, g, dim3(kWG), 0, s, tm,
-                     D, K, passes);
+                     D, own, passes);
             break;
         case TDS_F32:
             launch_k(k_sweep_batch<TM, float, float, kSweep32>, g, dim3(kWG), 0, s, tm,
-                     D, K, passes);
+                     D, own, passes);
             break;
         default:
             launch_k(k_sweep_batch<TM, float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D,
-                     K, passes);
+                     own, passes);
             break;
     }
 }
 
-hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t scans,
-                        int32_t bucket, int mode, int passes, bool halves, const KTime* tm,
-                        hipStream_t s) {
+hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items, const int32_t* own_scans,
+                        int64_t items, int64_t scans, int32_t bucket, int mode, int passes,
+                        bool halves, const KTime* tm, hipStream_t s) {
     if (items == 0) return hipSuccess;
     if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
     if (items > INT32_MAX) return hipErrorInvalidValue;
@@ -1303,27 +1293,27 @@ hipError_t launch_batch(const BatchDesc* D, int32_t K, int64_t items, int64_t sc
     const bool f64in = (mode == TDS_F64);
     if (bucket == 32) {
         if (f64in)
-            launch_k(k_beta_batch<32, double>, g, dim3(kWG), 0, s, tm, D, K);
+            launch_k(k_beta_batch<32, double>, g, dim3(kWG), 0, s, tm, D, own_items);
         else
-            launch_k(k_beta_batch<32, float>, g, dim3(kWG), 0, s, tm, D, K);
+            launch_k(k_beta_batch<32, float>, g, dim3(kWG), 0, s, tm, D, own_items);
     } else {
         if (f64in)
-            launch_k(k_beta_batch<64, double>, g, dim3(kWG), 0, s, tm, D, K);
+            launch_k(k_beta_batch<64, double>, g, dim3(kWG), 0, s, tm, D, own_items);
         else
-            launch_k(k_beta_batch<64, float>, g, dim3(kWG), 0, s, tm, D, K);
+            launch_k(k_beta_batch<64, float>, g, dim3(kWG), 0, s, tm, D, own_items);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (scans > 0) {
         launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanBatchThreads), 0, s,
-                 tm ? tm + 1 : nullptr, D, K);
+                 tm ? tm + 1 : nullptr, D, own_scans);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (bucket == 32)
-        batch_sweep<32>(D, K, items, mode, passes, false, s, tm ? tm + 2 : nullptr);
+        batch_sweep<32>(D, own_items, items, mode, passes, false, s, tm ? tm + 2 : nullptr);
     else
-        batch_sweep<64>(D, K, items, mode, passes, halves, s, tm ? tm + 2 : nullptr);
+        batch_sweep<64>(D, own_items, items, mode, passes, halves, s, tm ? tm + 2 : nullptr);
     return hipGetLastError();
 }
 
