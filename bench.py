@@ -416,7 +416,7 @@ def main():
     batched = args.workload in ("batch", "fourier")
     if batched:
         kname = "k_sweep_batch"
-    elif args.mode == "f32_refined" and W.plan.info().refined_halves:
+    elif args.mode != "f32" and W.plan.info().sweep_halves:
         kname = "k_sweep_halves"
     else:
         kname = "k_sweep_reg"

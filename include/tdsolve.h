@@ -92,9 +92,11 @@ typedef struct {
     double max_ratio;     /* max |Z_{k+1}/Z_k| over both sweeps; <= 1 under
                              dominance (proof of Theorem 4) */
     int32_t general;      /* 1 for a plan of tdsolve_prepare_general */
-    int32_t refined_halves; /* 1 if TDS_F32_REFINED sweeps every block in two
-                             halves (segments of 35..64 rows: a left half of
-                             32 interior rows, the middle row, the rest) */
+    int32_t sweep_halves; /* 1 if the modes with FP64 results (TDS_F64,
+                             TDS_F32_REFINED, TDS_F32_WIDE) sweep every block
+                             in two halves (segments of 35..64 rows: a left
+                             half of 32 interior rows, the middle row, the
+                             rest) */
 } tds_info;
 
 /* Preliminary step (Algorithm 3 step 1).  a: M-1 host doubles (may be NULL

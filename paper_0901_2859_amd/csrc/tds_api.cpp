@@ -562,7 +562,7 @@ int tdsolve_info(tds_handle h, tds_info* info) {
     info->refine_passes = h->passes;
     info->max_ratio = h->host.max_ratio;
     info->general = h->host.general;
-    info->refined_halves = h->has_halves ? 1 : 0;
+    info->sweep_halves = h->has_halves ? 1 : 0;
     return TDS_OK;
 }
 

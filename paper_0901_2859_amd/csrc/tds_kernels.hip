@@ -153,70 +153,88 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
     }
 }
 
-// beta_item with four right-hand sides per lane (FP32 input, N a multiple
-// of 4, F 16-byte aligned): each row access of a wavefront is one 1 KB span
-// read by 16-byte loads, a quarter of the load instructions.  Per
-// right-hand side the arithmetic is beta_item's (the same rows per
-// wavefront in the same order, the same reduction), so the weights are
-// bitwise the same.  Item (tile, j): block j x 256 right-hand sides.
-constexpr int kBeta4Rhs = 4 * kBetaRhs;
+// beta_item with V right-hand sides per lane read by one 16-byte load per
+// row (FP32 input: V = 4; FP64 input: V = 2), N a multiple of V and F
+// 16-byte aligned: each row access of a wavefront is one 1 KB span, a V-th
+// of the load instructions.  Per right-hand side the arithmetic is
+// beta_item's (the same rows per wavefront in the same order, the same
+// reduction), so the weights are bitwise the same.  Item (tile, j): block j
+// x 64 V right-hand sides.
+template <typename Fin>
+struct Vec16;                  // 16 bytes of Fin
+template <>
+struct Vec16<float> {
+    static constexpr int V = 4;
+    using type = float4;
+};
+template <>
+struct Vec16<double> {
+    static constexpr int V = 2;
+    using type = double2;
+};
 
-template <int TMAX>
-__device__ __forceinline__ void beta_item4(const DevTables& T, const float* __restrict__ F,
-                                           int64_t N, int32_t j, int64_t tile,
-                                           double* __restrict__ betaR,
-                                           double* __restrict__ betaL,
-                                           double2* __restrict__ red) {
+template <int TMAX, typename Fin>
+__device__ __forceinline__ void beta_item_vec(const DevTables& T, const Fin* __restrict__ F,
+                                              int64_t N, int32_t j, int64_t tile,
+                                              double* __restrict__ betaR,
+                                              double* __restrict__ betaL,
+                                              double2* __restrict__ red) {
     constexpr int TQ = TMAX / kBetaWaves;
-    const int64_t n0 = tile * kBeta4Rhs;
+    constexpr int V = Vec16<Fin>::V;
+    using VT = typename Vec16<Fin>::type;
+    const int64_t n0 = tile * (V * kBetaRhs);
     if (n0 >= N) return;                                  // uniform per workgroup
     const int64_t lo = cst(T.starts)[j];
     const int t = (int)(cst(T.starts)[j + 1] - lo);
     const int lane = threadIdx.x % kBetaRhs;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kBetaRhs);
-    const bool live = n0 + 4 * lane < N;
-    // lanes past N read the last group of four columns and store nothing
-    const uint32_t off = (uint32_t)(live ? 4 * lane : N - 4 - n0) * sizeof(float);
-    const float* fb = F + lo * N + n0;
+    const bool live = n0 + V * lane < N;
+    // lanes past N read the last group of V columns and store nothing
+    const uint32_t off = (uint32_t)(live ? V * lane : N - V - n0) * sizeof(Fin);
+    const Fin* fb = F + lo * N + n0;
     const int r0 = wv * TQ;
     const cptr<double2> w = cst(T.wpad + (int64_t)j * TMAX + r0);
-    float4 v[TQ];
+    VT v[TQ];
 #pragma unroll
     for (int r = 0; r < TQ; ++r) {
         const int row = r0 + r < t ? r0 + r : t - 1;
-        v[r] = at_off((const float4*)(fb + (int64_t)row * N), off);
+        v[r] = at_off((const VT*)(fb + (int64_t)row * N), off);
     }
-    double bR[4] = {0.0, 0.0, 0.0, 0.0}, bL[4] = {0.0, 0.0, 0.0, 0.0};
+    double bR[V], bL[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) bR[q] = bL[q] = 0.0;
 #pragma unroll
     for (int r = 0; r < TQ; ++r) {
         const double cR = w[r].x, cL = w[r].y;
-        const float e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+        Fin e[V];
+        __builtin_memcpy(e, &v[r], sizeof(VT));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < V; ++q) {
             bR[q] = fma(cR, (double)e[q], bR[q]);
             bL[q] = fma(cL, (double)e[q], bL[q]);
         }
     }
     if (wv > 0)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            red[((wv - 1) * 4 + q) * kBetaRhs + lane] = make_double2(bR[q], bL[q]);
+        for (int q = 0; q < V; ++q)
+            red[((wv - 1) * V + q) * kBetaRhs + lane] = make_double2(bR[q], bL[q]);
     __syncthreads();
     if (wv == 0 && live) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < V; ++q)
 #pragma unroll
             for (int k = 0; k < kBetaWaves - 1; ++k) {
-                const double2 p = red[(k * 4 + q) * kBetaRhs + lane];
+                const double2 p = red[(k * V + q) * kBetaRhs + lane];
                 bR[q] += p.x;
                 bL[q] += p.y;
             }
-        if (j < T.P - 1)
-            *(double4*)&betaR[(int64_t)j * N + n0 + 4 * lane] =
-                make_double4(bR[0], bR[1], bR[2], bR[3]);
-        if (j > 0)
-            *(double4*)&betaL[(int64_t)j * N + n0 + 4 * lane] =
-                make_double4(bL[0], bL[1], bL[2], bL[3]);
+        double* oR = &betaR[(int64_t)j * N + n0 + V * lane];
+        double* oL = &betaL[(int64_t)j * N + n0 + V * lane];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            if (j < T.P - 1) oR[q] = bR[q];
+            if (j > 0) oL[q] = bL[q];
+        }
     }
 }
 
@@ -805,12 +823,13 @@ constexpr int sweep_min_waves() {
 
 // ==========================================================================
 // single-matrix kernels: grid (RHS tiles, blocks)
-template <int TMAX>
-__global__ __launch_bounds__(kWG) void k_beta4(DevTables T, const float* __restrict__ F, int64_t N,
-                                               double* __restrict__ betaR,
-                                               double* __restrict__ betaL) {
-    __shared__ double2 red[(kBetaWaves - 1) * 4 * kBetaRhs];
-    beta_item4<TMAX>(T, F, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, betaR, betaL, red);
+template <int TMAX, typename Fin>
+__global__ __launch_bounds__(kWG) void k_beta_vec(DevTables T, const Fin* __restrict__ F,
+                                                  int64_t N, double* __restrict__ betaR,
+                                                  double* __restrict__ betaL) {
+    __shared__ double2 red[(kBetaWaves - 1) * Vec16<Fin>::V * kBetaRhs];
+    beta_item_vec<TMAX, Fin>(T, F, N, (int32_t)blockIdx.y, (int64_t)blockIdx.x, betaR, betaL,
+                             red);
 }
 
 template <int TMAX, typename Fin>
@@ -838,7 +857,7 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     // the FP32 elimination values
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
     // FP32 input: the blocks in reverse, so the rows the beta pass read last
-    // are swept first (its 16-byte-load tiles are this kernel's 256 RHS, so
+    // are swept first (k_beta_vec's FP32 tiles are this kernel's 256 RHS, so
     // each tile already runs on the XCD that read it; see k_sweep_halves)
     const int32_t j = std::is_same<Fin, float>::value ? (int32_t)(gridDim.y - 1 - blockIdx.y)
                                                       : (int32_t)blockIdx.y;
@@ -941,23 +960,22 @@ __global__ __launch_bounds__(2 * RHS, 4) void k_sweep_halves(DevTables H,
                                                              int passes) {
     __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * RHS : 1];
     __shared__ double s_q[2 * RHS];
-    // Order of the work on FP32 input: the blocks in reverse, so the rows the
-    // beta pass read last are swept first, and with tile counts that are a
-    // multiple of 2 kXcdsSweep each tile on the XCD that read its columns in
-    // the beta pass (k_beta4: two tiles of this kernel per beta tile;
-    // workgroup w runs on XCD w % 8).  Poisson 4096 x 4096: sweep 35.3-36.7
-    // us in the plain order, 33.8 us reversed, 32.1-33.0 us with both; the
-    // bytes fetched past L2 stay the same, so the gain is in how fast those
-    // fetches are served.  FP64 input (k_beta, 64-RHS tiles) keeps the plain
-    // order, which measured faster there.
+    // Order of the work: the blocks in reverse, so the rows the beta pass
+    // read last are swept first, and each tile on the XCD that read its
+    // columns in the beta pass (workgroup w runs on XCD w % 8; k_beta_vec's
+    // tiles are 256 RHS on FP32 input, two tiles of this kernel, remapped
+    // when the tile count is a multiple of 2 kXcdsSweep, and 128 RHS on FP64
+    // input, the same tiles).  Poisson 4096 x 4096 on FP32 input: sweep
+    // 35.3-36.7 us in the plain order, 33.8 us reversed, 32.1-33.0 us with
+    // both; the bytes fetched past L2 stay the same, so the gain is in how
+    // fast those fetches are served.
     uint32_t b = blockIdx.x;
-    int32_t j = (int32_t)blockIdx.y;
+    const int32_t j = (int32_t)(gridDim.y - 1 - blockIdx.y);
     if constexpr (std::is_same<Fin, float>::value) {
         if (gridDim.x % (2 * kXcdsSweep) == 0) {
             const uint32_t q = b % kXcdsSweep, r = b / kXcdsSweep;
             b = 2 * (q + kXcdsSweep * (r / 2)) + (r % 2);
         }
-        j = (int32_t)(gridDim.y - 1 - blockIdx.y);
     }
     halves_item<RHS, Fin, KIND, GEN>(H, F, X, N, j, (int64_t)b, xsep, passes, s_f, s_q);
 }
@@ -1089,16 +1107,22 @@ int32_t rows_bucket(int32_t max_rows) {
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
                        double* betaL, hipStream_t s, const KTime* tm) {
     if (t.P < 2 || N == 0) return hipSuccess;
-    // FP32 input in rows of whole 16-byte groups: four right-hand sides per lane
-    if (f32 && N % 4 == 0 && ((uintptr_t)F & 15) == 0 &&
+    // rows of whole 16-byte groups: four (FP32) or two (FP64) right-hand
+    // sides per lane
+    const int V = f32 ? 4 : 2;
+    if (N % V == 0 && ((uintptr_t)F & 15) == 0 &&
         (t.wpad_rows == 32 || t.wpad_rows == 64 || t.wpad_rows == 128)) {
-        const dim3 g4((unsigned)((N + kBeta4Rhs - 1) / kBeta4Rhs), (unsigned)t.P, 1);
-        if (t.wpad_rows == 32)
-            launch_k(k_beta4<32>, g4, dim3(kWG), 0, s, tm, t, (const float*)F, N, betaR, betaL);
-        else if (t.wpad_rows == 64)
-            launch_k(k_beta4<64>, g4, dim3(kWG), 0, s, tm, t, (const float*)F, N, betaR, betaL);
-        else
-            launch_k(k_beta4<128>, g4, dim3(kWG), 0, s, tm, t, (const float*)F, N, betaR, betaL);
+        const dim3 gv((unsigned)((N + V * kBetaRhs - 1) / (V * kBetaRhs)), (unsigned)t.P, 1);
+#define TDS_BETA_VEC(TM, FT) \
+    launch_k(k_beta_vec<TM, FT>, gv, dim3(kWG), 0, s, tm, t, (const FT*)F, N, betaR, betaL)
+        if (t.wpad_rows == 32) {
+            if (f32) TDS_BETA_VEC(32, float); else TDS_BETA_VEC(32, double);
+        } else if (t.wpad_rows == 64) {
+            if (f32) TDS_BETA_VEC(64, float); else TDS_BETA_VEC(64, double);
+        } else {
+            if (f32) TDS_BETA_VEC(128, float); else TDS_BETA_VEC(128, double);
+        }
+#undef TDS_BETA_VEC
         return hipGetLastError();
     }
     const dim3 g((unsigned)((N + kBetaRhs - 1) / kBetaRhs), (unsigned)t.P, 1);

@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("P", ctypes.c_int32), ("max_block", ctypes.c_int32),
                 ("dominant", ctypes.c_int32), ("refine_passes", ctypes.c_int32),
                 ("max_ratio", ctypes.c_double), ("general", ctypes.c_int32),
-                ("refined_halves", ctypes.c_int32)]
+                ("sweep_halves", ctypes.c_int32)]
 
 
 def lib():

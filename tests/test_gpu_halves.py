@@ -60,7 +60,7 @@ def test_halves_match_oracle(M, N, P, halves, mode):
     F = F32.astype(np.float64)
     ref = oracle.thomas(a, b, F)
     plan = t.Plan(a, b, P)
-    assert plan.P == P and plan.info().refined_halves == halves
+    assert plan.P == P and plan.info().sweep_halves == halves
     Fd = torch.from_numpy(F32).to(DEV)
     X = plan.solve(Fd.double() if mode == "f64" else Fd, mode=mode).cpu().numpy()
     e = np.max(np.abs(X - ref), axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
@@ -103,7 +103,7 @@ def test_refined_halves_general_matrix():
     low, upp = np.concatenate([[0.0], lo]), np.concatenate([up, [0.0]])
     ref = np.stack([oracle.tridiag_general(low, d, upp, F[:, n]) for n in range(N)], 1)
     plan = t.Plan.general(lo, d, up, P)
-    assert plan.info().refined_halves == 1
+    assert plan.info().sweep_halves == 1
     X = plan.solve(torch.from_numpy(F32).to(DEV), mode="f32_refined").cpu().numpy()
     scale = np.max(np.abs(ref), axis=0)
     assert np.max(np.abs(X - ref).max(axis=0) / scale) <= 1e-11
