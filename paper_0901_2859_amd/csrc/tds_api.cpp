@@ -17,7 +17,8 @@ using namespace tds;
 struct tds_plan {
     HostTables host;
     DevTables dev;
-    // the refined sweep's half-block tables (half_tables), when the blocks fit
+    // half-block tables (half_tables) of the sweeps with FP64 results, when
+    // the blocks fit them
     bool has_halves = false;
     DevTables halves;
     void* dev_mem = nullptr;
@@ -193,7 +194,7 @@ int upload(tds_plan* h) {
     if (hipGetDevice(&h->device) != hipSuccess) return TDS_EHIP;
     std::vector<unsigned char> img;
     h->dev = append_image(h->host, rows_bucket(h->host.max_rows), img);
-    // blocks of 33..64 rows: the refined sweep takes them in halves
+    // blocks of 35..64 rows: the sweeps with FP64 results take them in halves
     HostTables hh;
     h->has_halves = rows_bucket(h->host.max_rows) == 64 &&
                     half_tables(h->host, kHalfRows, hh) == TDS_OK;
@@ -667,8 +668,8 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a, const double* const
     std::vector<unsigned char> img;
     h->devs.resize(K);
     for (int32_t k = 0; k < K; ++k) h->devs[k] = append_image(h->hosts[k], bucket, img);
-    // 64-row bucket: the refined sweep takes the blocks in halves when every
-    // matrix's blocks fit them (one sweep kernel for the whole batch)
+    // 64-row bucket: the sweeps with FP64 results take the blocks in halves
+    // when every matrix's blocks fit them (one sweep kernel for the batch)
     h->has_halves = bucket == 64;
     std::vector<HostTables> hh(h->has_halves ? K : 0);
     for (int32_t k = 0; k < K && h->has_halves; ++k)

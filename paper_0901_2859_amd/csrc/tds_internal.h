@@ -85,8 +85,9 @@ int32_t default_blocks(int64_t M);
 // 2 P (P-1) doubles (16 MB at 1024) and its work grows as P^2 per
 // right-hand side.
 constexpr int32_t kDenseMaxBlocks = 1024;
-// Rows of the left half when the refined sweep splits a block in two
-// (k_sweep_halves): blocks of kHalfRows + 2 .. 2 kHalfRows + 1 interior rows.
+// Rows of the left half when the sweeps with FP64 results split a block in
+// two (k_sweep_halves): blocks of kHalfRows + 2 .. 2 kHalfRows + 1 interior
+// rows.
 constexpr int32_t kHalfRows = 32;
 // The partition with every block of `o` split into a left half of `lead`
 // interior rows, a middle row and a right half (at least one row), as
@@ -126,7 +127,7 @@ hipError_t launch_iface_dense(const double* Kt, int32_t Pc, int32_t Mr, int32_t 
                               const double* betaR, const double* betaL, double* xsep, int64_t N,
                               hipStream_t s, const KTime* tm = nullptr);
 // `halves` (may be null): the half-block tables of t (half_tables), used by
-// the refined sweep of blocks that fit them
+// the sweeps with FP64 results of blocks that fit them
 hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         int mode, int passes, const double* xsep,
                         hipStream_t s, const KTime* tm = nullptr,
@@ -167,7 +168,7 @@ struct BatchDesc {
 // The three steps for all matrices of a batch: one launch each.  `bucket`
 // is the common register-sweep row bucket (32 or 64); `halves`: every
 // matrix's BatchDesc::H holds its half-block tables (bucket 64), and the
-// refined sweep takes the blocks in halves.
+// sweeps with FP64 results take the blocks in halves.
 // `tm` (may be null): start/stop events of the beta, interface and sweep
 // launches, in that order (the interface pair stays unrecorded when no
 // matrix has interface rows, scans == 0).

@@ -13,7 +13,8 @@
 // when their pointers come from a descriptor table, as in the batch.)
 //
 //   beta   eq. beta_symn: beta^R_j, beta^L_j of block j (FP64 accumulation;
-//          FP32 series with N % 4 == 0 read four right-hand sides per lane).
+//          rows of whole 16-byte groups are read four (FP32) or two (FP64)
+//          right-hand sides per lane).
 //   iface  Theorem 2 (eq. theor_2): x at the interface rows, in one of three
 //          orders: the two first-order recurrences S^R_{k+1} = rho_k S^R_k +
 //          beta^R_k and S^L_k = beta^L_k + lam_k S^L_{k+1}, x(s_k) = S^R_k +
@@ -21,8 +22,8 @@
 //          double sum itself as one dense product on the FP64 matrix cores.
 //   sweep  Lemma 1 / Algorithm 1 step 3: the sweep inside each block with
 //          both boundary values known; X leaves with streaming stores.  The
-//          refined sweep of 35..64-row blocks takes each block in two
-//          halves on separate wavefronts, joined at the middle row.
+//          sweeps with FP64 results take 35..64-row blocks in two halves on
+//          separate wavefronts, joined at the middle row.
 //
 // Each step is a device function over one work item; the single-matrix
 // kernels index items by their 2-D grid, the batch kernels (many matrices of
@@ -864,13 +865,14 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     sweep_item<TMAX, Fin, Xout, KIND, GEN>(T, F, X, N, j, (int64_t)blockIdx.x, xsep, passes, s_f);
 }
 
-// Refined sweep of a block in two halves (tables from half_tables): block
-// j's interior rows i0..i1 are a left half of kHalfRows rows, the middle
-// row m = i0 + kHalfRows and a right half m+1..i1.  Wavefronts 0-1 take the
-// left half of 128 right-hand sides, wavefronts 2-3 the right half of the
-// same ones (RHS = 128; with RHS = 256, 8 wavefronts of which 0-3 take the
-// left half); each half is solved with zero boundary values (refined_solve).
-// The value at m then follows from row m's equation with its neighbours
+// Sweep of a block in two halves for the modes with FP64 results (tables
+// from half_tables): block j's interior rows i0..i1 are a left half of
+// kHalfRows rows, the middle row m = i0 + kHalfRows and a right half
+// m+1..i1.  Wavefronts 0-1 take the left half of 128 right-hand sides,
+// wavefronts 2-3 the right half of the same ones (RHS = 128; with RHS =
+// 256, 8 wavefronts of which 0-3 take the left half); each half is solved
+// with zero boundary values (refined_solve, or one FP64 sweep).  The value
+// at m then follows from row m's equation with its neighbours
 // written by superposition (x_{m-1} through the left half, x_{m+1} through
 // the right one):
 //     x_m = (f_m - A[m][m-1] qA - A[m][m+1] qB) mid_inv,
