@@ -134,3 +134,28 @@ def test_uneven_batch_full_size_sampled(tmp_path, monkeypatch):
         cols = sorted({0, it["N"] // 2, it["N"] - 1})
         X = Xs[k][:, cols].cpu().numpy()
         _check(it["a"], it["b"], it["F"][:, cols].astype(np.float64), X, P_l[k])
+
+
+def test_batch_many_small_matrices():
+    # 600 matrices of 2..200 rows and 0..40 right-hand sides: most own one to
+    # a few work items, so neighbouring items belong to different matrices
+    # (the per-item owner table), and some series are empty
+    rng = np.random.default_rng(31)
+    K = 600
+    Ms = rng.integers(2, 201, size=K)
+    Ns = rng.integers(0, 41, size=K)
+    a_l, b_l, F_l = [], [], []
+    for M, N in zip(Ms, Ns):
+        a = rng.uniform(-1, -0.5, size=M - 1)
+        b = 2.2 + rng.uniform(0, 1, size=M)
+        a_l.append(a)
+        b_l.append(b)
+        F_l.append(rng.uniform(-1, 1, size=(M, N)).astype(np.float32))
+    print(f"batch K={K} small matrices", flush=True)
+    bp = t.BatchPlan(a_l, b_l)
+    Xs = bp.solve([torch.from_numpy(F).to(DEV) for F in F_l], mode="f32_refined")
+    for k in range(K):
+        if Ns[k] == 0:
+            continue
+        P = t.default_blocks(int(Ms[k]))
+        _check(a_l[k], b_l[k], F_l[k].astype(np.float64), Xs[k].cpu().numpy(), P)
