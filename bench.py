@@ -79,6 +79,27 @@ def parse():
     return p.parse_args()
 
 
+def copy_bandwidth(torch, dev, mib=512, reps=20):
+    """Measured HBM rate of a plain device copy (torch's copy kernel, `mib`
+    MiB read and written per launch), the practical ceiling the sweeps are
+    read against; GB/s counts the bytes read plus the bytes written."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    gbs = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    return {"kernel": "torch copy_", "bytes_per_launch": 2 * (mib << 20), "ms_per_launch": round(ms, 5),
+            "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def time_steps(solve, n_sets, steps, warmup, graph, timed_plan, torch):
     """ms per step over `steps` calls of solve(k) (eager launches, or replays
     of one captured HIP graph per buffer set), then the per-phase split from
@@ -438,6 +459,7 @@ def main():
                 continue
             compare[mode] = run(mode, max(10, args.steps // 2), max(3, args.warmup // 2))
 
+    copy = None if args.no_compare else copy_bandwidth(torch, dev)
     cpu = None if args.no_cpu else W.cpu_baseline(args.cpu_seconds)
 
     out = {
@@ -467,6 +489,7 @@ def main():
         "prepare_ms": round(W.prepare_ms, 3),
         "roofline": roofline,
         "compare": compare,
+        "copy": copy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
