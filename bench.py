@@ -79,6 +79,36 @@ def parse():
     return p.parse_args()
 
 
+def oracle_one_thread(a, b, F, seconds):
+    """unknowns/s of the oracle on one host thread: a child process (OpenMP's
+    thread count is fixed when the library loads) that touches no GPU."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    with tempfile.TemporaryDirectory() as d:
+        for name, arr in (("a", a), ("b", b), ("F", F)):
+            np.save(os.path.join(d, name + ".npy"), np.ascontiguousarray(arr))
+        code = (
+            "import sys, time, numpy as np\n"
+            f"sys.path.insert(0, {ROOT!r})\n"
+            "import oracle\n"
+            f"d = {d!r}\n"
+            "a, b, F = (np.load(d + '/' + n + '.npy') for n in ('a', 'b', 'F'))\n"
+            "reps, t0 = 0, time.perf_counter()\n"
+            "while True:\n"
+            "    oracle.thomas(a, b, F)\n"
+            "    reps += 1\n"
+            f"    if time.perf_counter() - t0 >= {float(seconds)}:\n"
+            "        break\n"
+            "print(reps * F.shape[0] * F.shape[1] / (time.perf_counter() - t0))\n")
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           timeout=seconds + 120, env=dict(os.environ, OMP_NUM_THREADS="1"))
+    if r.returncode != 0:
+        return None
+    return float(r.stdout.strip().splitlines()[-1])
+
+
 def copy_bandwidth(torch, dev, mib=512, reps=20):
     """Measured HBM rate of a plain device copy (torch's copy kernel, `mib`
     MiB read and written per launch), the practical ceiling the sweeps are
@@ -219,10 +249,15 @@ class Single:
             if time.perf_counter() - t0 >= seconds:
                 break
         el = time.perf_counter() - t0
+        one = oracle_one_thread(self.a, self.b, Fw[:, :512], seconds / 2)
         return {"value": reps * self.unknowns / el, "unit": "unknowns/s",
                 "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"FP64 sequential sweep per RHS (OpenMP over RHS) on the full "
-                          f"{self.M}x{self.N} series, repeated {reps}x over {el:.1f} s"}
+                          f"{self.M}x{self.N} series, repeated {reps}x over {el:.1f} s",
+                "value_1_thread": one,
+                "sample_1_thread": f"the first 512 right-hand sides, one thread "
+                                   f"(OMP_NUM_THREADS=1 in a child process), about "
+                                   f"{seconds / 2:.0f} s"}
 
 
 class Batch:
