@@ -162,6 +162,14 @@ def time_steps(solve, n_sets, steps, warmup, graph, timed_plan, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(stop)
+    # per-step distribution, in a separate pass (events around every step)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
+        step(k)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
     del graphs
     # phase split (events between the launches of each solve)
     timed_plan.timing(True)
@@ -172,6 +180,7 @@ def time_steps(solve, n_sets, steps, warmup, graph, timed_plan, torch):
     ms_beta, ms_iface, ms_sweep, calls = timed_plan.timing_read()
     timed_plan.timing(False)
     return dict(ms_per_step=ms_total / steps, wall_s=wall,
+                ms_step_median=per[steps // 2], ms_step_min=per[0],
                 ms_beta=ms_beta / calls, ms_iface=ms_iface / calls,
                 ms_sweep=ms_sweep / calls, launch="graph" if graph else "eager")
 
@@ -519,6 +528,8 @@ def main():
                       "interface": round(main_r["ms_iface"], 5),
                       "sweep": round(main_r["ms_sweep"], 5)},
         "warm_ms_per_step": main_r.get("warm_ms_per_step"),
+        "ms_per_step_median": round(main_r["ms_step_median"], 5),
+        "ms_per_step_min": round(main_r["ms_step_min"], 5),
         "r2_max": main_r["r2_max"],
         "eta_max": main_r["eta_max"],
         "prepare_ms": round(W.prepare_ms, 3),
