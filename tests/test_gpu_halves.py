@@ -123,3 +123,24 @@ def test_refined_halves_reproducible_and_in_place_of_rows():
     plan.solve(F, X2, mode="f32_refined")
     assert not torch.isnan(X1).any()
     assert torch.equal(X1, X2)
+
+
+@pytest.mark.parametrize("mode", ["f32_refined", "f64", "f32_wide"])
+def test_unaligned_series_takes_the_scalar_beta_path_bitwise(mode):
+    # F starting one element past a 16-byte boundary cannot be read by the
+    # 16-byte-load beta kernel; the one-RHS-per-lane kernel forms the same
+    # weights in the same order, so X is bitwise that of the aligned solve
+    rng = np.random.default_rng(17)
+    M, N, P = 4096, 512, 64
+    a = rng.uniform(-1, -0.5, size=M - 1)
+    b = 2.2 + rng.uniform(0, 1, size=M)
+    dt = torch.float64 if mode == "f64" else torch.float32
+    F = torch.from_numpy(rng.uniform(-1, 1, size=(M, N))).to(DEV, dt)
+    buf = torch.empty(M * N + 1, dtype=dt, device=DEV)
+    Fu = buf[1:].view(M, N)
+    Fu.copy_(F)
+    assert Fu.data_ptr() % 16 != 0 and F.data_ptr() % 16 == 0
+    plan = t.Plan(a, b, P)
+    X1 = plan.solve(F, mode=mode)
+    X2 = plan.solve(Fu, mode=mode)
+    assert torch.equal(X1, X2)
