@@ -301,6 +301,21 @@ int tdsolve_batch_autotune(int32_t K, const double* const* a,
                            const int64_t* N, int32_t mode, int32_t reps,
                            int32_t* P_out, double* ms_out, void* stream);
 
+/* Scaled strided copy dst = alpha * src of an S x M x L array of doubles
+ * (f64 != 0) or floats, for the drivers that move the series between a
+ * mesh layout and the RHS-interleaved layout (section "Variable separation
+ * method": the harmonics of S problems become one series per harmonic).
+ * Element (s, i, l) lives at src[s*ss[0] + i*ss[1] + l*ss[2]] and
+ * dst[s*ds[0] + i*ds[1] + l*ds[2]] (device pointers; strides in elements,
+ * host arrays of 3, non-negative).  Tiled through LDS per i, so a copy that
+ * is contiguous along l on one side and along s on the other (a transpose)
+ * reads and writes whole rows.  src and dst must not overlap.
+ * Errors: TDS_EINVAL (null pointers with a non-empty array, negative sizes
+ * or strides), TDS_EUNSUPPORTED (M > 65535), TDS_EHIP. */
+int tdsolve_strided_copy(const void* src, void* dst, int32_t f64, int64_t S, int64_t M,
+                         int64_t L, const int64_t* ss, const int64_t* ds, double alpha,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -847,3 +847,17 @@ int tdsolve_status(tds_handle h, void* stream, double* backward_err, int32_t* pa
 }
 
 }  // extern "C"
+
+int tdsolve_strided_copy(const void* src, void* dst, int32_t f64, int64_t S, int64_t M, int64_t L,
+                         const int64_t* ss, const int64_t* ds, double alpha, void* stream) {
+    if (S < 0 || M < 0 || L < 0 || !ss || !ds) return TDS_EINVAL;
+    if (S == 0 || M == 0 || L == 0) return TDS_OK;
+    if (!src || !dst) return TDS_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (ss[k] < 0 || ds[k] < 0) return TDS_EINVAL;
+    if (M > 65535) return TDS_EUNSUPPORTED;
+    if (launch_strided_copy(src, dst, f64 != 0, S, M, L, ss, ds, alpha, (hipStream_t)stream) !=
+        hipSuccess)
+        return TDS_EHIP;
+    return TDS_OK;
+}

@@ -109,6 +109,38 @@ __global__ __launch_bounds__(kWG) void k_adjoint_reduce(const Xin* __restrict__ 
     }
 }
 
+// --------------------------------------------------------------------------
+// Scaled strided copy of an S x M x L array through 64 x 64 LDS tiles of
+// (s, l) per i: the reads walk l fastest, the writes walk s fastest, so a
+// layout change between (s, i, l) and (l, i, s) moves whole rows on both
+// sides.  Grid: (tiles of l x tiles of s, M).
+constexpr int kCopyTile = 64;
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_strided_copy(const T* __restrict__ src, T* __restrict__ dst,
+                                                      int64_t S, int64_t L, int64_t ss0,
+                                                      int64_t ss1, int64_t ss2, int64_t ds0,
+                                                      int64_t ds1, int64_t ds2, T alpha) {
+    __shared__ T tile[kCopyTile][kCopyTile + 1];
+    const int64_t tl = (L + kCopyTile - 1) / kCopyTile;
+    const int64_t l0 = (int64_t)(blockIdx.x % tl) * kCopyTile;
+    const int64_t s0 = (int64_t)(blockIdx.x / tl) * kCopyTile;
+    const int64_t i = blockIdx.y;
+    const int c = threadIdx.x % kCopyTile, r0 = threadIdx.x / kCopyTile;   // 4 rows per pass
+    constexpr int kRows = kWG / kCopyTile;
+#pragma unroll 4
+    for (int r = r0; r < kCopyTile; r += kRows) {
+        const int64_t s = s0 + r, l = l0 + c;
+        if (s < S && l < L) tile[r][c] = src[s * ss0 + i * ss1 + l * ss2];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = r0; r < kCopyTile; r += kRows) {
+        const int64_t l = l0 + r, s = s0 + c;
+        if (s < S && l < L) dst[s * ds0 + i * ds1 + l * ds2] = alpha * tile[c][r];
+    }
+}
+
 // ==========================================================================
 // launchers
 hipError_t launch_residual(const DevTables& t, const void* F, const void* X, int64_t N,
@@ -179,6 +211,23 @@ hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipS
     else
         hipLaunchKernelGGL(k_fill_uniform<double>, dim3(blocks), dim3(kWG), 0, s, (double*)p, n,
                            seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_copy(const void* src, void* dst, bool f64, int64_t S, int64_t M,
+                               int64_t L, const int64_t* ss, const int64_t* ds, double alpha,
+                               hipStream_t s) {
+    if (S == 0 || M == 0 || L == 0) return hipSuccess;
+    const int64_t tiles = ((L + kCopyTile - 1) / kCopyTile) * ((S + kCopyTile - 1) / kCopyTile);
+    if (tiles > 0x7fffffffLL || M > 65535) return hipErrorInvalidValue;
+    const dim3 g((unsigned)tiles, (unsigned)M, 1);
+    if (f64)
+        hipLaunchKernelGGL(k_strided_copy<double>, g, dim3(kWG), 0, s, (const double*)src,
+                           (double*)dst, S, L, ss[0], ss[1], ss[2], ds[0], ds[1], ds[2], alpha);
+    else
+        hipLaunchKernelGGL(k_strided_copy<float>, g, dim3(kWG), 0, s, (const float*)src,
+                           (float*)dst, S, L, ss[0], ss[1], ss[2], ds[0], ds[1], ds[2],
+                           (float)alpha);
     return hipGetLastError();
 }
 

@@ -191,6 +191,12 @@ hipError_t launch_adjoint_reduce(const DevTables& t, const void* X,
                                  int64_t N, float* g32, double* ga,
                                  double* gb, hipStream_t s);
 
+// dst = alpha src over S x M x L elements with the given element strides
+// (tdsolve_strided_copy)
+hipError_t launch_strided_copy(const void* src, void* dst, bool f64, int64_t S, int64_t M,
+                               int64_t L, const int64_t* ss, const int64_t* ds, double alpha,
+                               hipStream_t s);
+
 // Rows of partial sums used by the residual and adjoint reductions.
 constexpr int kReduceRowChunk = 64;
 

@@ -14,8 +14,8 @@ one fixed matrix per harmonic with S right-hand sides (eq. poisson_end):
 N2-1 series of the kind the library solves, handed to it as one batch.  The
 sine transforms along y are FFTs of the odd extension (torch.fft); the
 transposes that bring the S problems next to each other (RHS-interleaved
-layout per harmonic) are torch copies.  Only the tridiagonal series run in
-the library's kernels.
+layout per harmonic) and back are the library's tiled strided copies
+(tdsolve_strided_copy), the tridiagonal series its batch solve.
 
 Layout: f and u are (S, N1-1, N2-1) device tensors, u[n, i-1, j-1] = u_n at
 mesh point (i, j).
@@ -90,9 +90,13 @@ class FourierPoisson2D:
         # strided multiply (scale and transpose in one pass)
         scale = self.h1 ** 2 * 2.0 / self.N2
         rhs = torch.empty((L, M, S), dtype=wdt, device=f.device)
-        torch.mul(_dst1_view(f.to(wdt)), -scale, out=rhs.permute(2, 1, 0))
+        t.strided_copy(rhs.permute(2, 1, 0), _dst1_view(f.to(wdt)), -scale, stream=stream)
         X = self.plan.solve_stacked(rhs, mode=self.mode, stream=stream)
-        return dst1(X.permute(2, 1, 0))                       # back to mesh values in y
+        # back to mesh values in y: X (l, i, S) into the padded odd-extension
+        # rows of the inverse transform, again by one tiled transposing copy
+        Y = torch.zeros((S, M, 2 * (L + 1)), dtype=X.dtype, device=X.device)
+        t.strided_copy(Y[..., 1:L + 1], X.permute(2, 1, 0), 1.0, stream=stream)
+        return -torch.fft.rfft(Y, dim=-1).imag[..., 1:L + 1]
 
     @staticmethod
     def eigen_rhs(N1, N2, k, l, h1=None, h2=None):

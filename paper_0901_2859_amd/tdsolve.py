@@ -34,7 +34,7 @@ SYMBOLS = [
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
     "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
-    "tdsolve_status",
+    "tdsolve_status", "tdsolve_strided_copy",
 ]
 
 _lib = None
@@ -84,6 +84,7 @@ def lib():
     L.tdsolve_batch_prepare.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(vp)]
     L.tdsolve_batch_series.argtypes = [vp, vp, vp, vp, i32, vp]
     L.tdsolve_status.argtypes = [vp, vp, vp, vp]
+    L.tdsolve_strided_copy.argtypes = [vp, vp, i32, i64, i64, i64, vp, vp, ctypes.c_double, vp]
     L.tdsolve_timing_enable.argtypes = [vp, i32]
     L.tdsolve_timing_read.argtypes = [vp, vp, vp]
     L.tdsolve_autotune.argtypes = [dp, dp, i64, i64, i32, i32, vp, vp, vp]
@@ -170,6 +171,27 @@ def _stream_ptr(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def strided_copy(dst, src, alpha: float = 1.0, stream=None):
+    """dst = alpha * src for two device views of one shape (S, M, L) and one
+    dtype (float32 or float64), any non-negative strides
+    (tdsolve_strided_copy: LDS tiles of (s, l) per i, so a transposing copy
+    reads and writes whole rows)."""
+    import torch
+    if tuple(dst.shape) != tuple(src.shape) or dst.dim() != 3:
+        raise ValueError("dst and src must be views of one (S, M, L) shape")
+    if dst.dtype != src.dtype or src.dtype not in (torch.float32, torch.float64):
+        raise TypeError("dst and src must both be float32 or both float64")
+    if not (dst.is_cuda and src.is_cuda):
+        raise ValueError("dst and src must be device tensors")
+    S, M, L = src.shape
+    ss = np.array(src.stride(), dtype=np.int64)
+    ds = np.array(dst.stride(), dtype=np.int64)
+    _check(lib().tdsolve_strided_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                      int(src.dtype == torch.float64), S, M, L, _ptr(ss), _ptr(ds),
+                                      float(alpha), _stream_ptr(stream)), "tdsolve_strided_copy")
+    return dst
 
 
 def _status(h, stream):
