@@ -48,6 +48,7 @@ def _r2(a, b, F, X):
     (720, 200, 20, 1),     # 36-row segments
     (50, 10, 1, 1),        # one block, no interface rows
     (64 * 30 - 7, 257, 30, 1),  # 64 and 63 rows; one live column in the last workgroup
+    (2048, 2000, 32, 1),   # 16 tiles of 128: the XCD-matched tile order, last tile partial
     (680, 70, 20, 0),      # 34-row segments: below the split, swept whole
 ])
 @pytest.mark.parametrize("mode", ["f32_refined", "f64", "f32_wide"])
