@@ -270,13 +270,19 @@ def interface_dichotomy(prep, bR, bL):
 
 
 # ------------------------------------------------------ metrics
-def residual_metrics(a, b, F, X, X_ref=None):
-    """Per-RHS max over the series of: normwise backward error eta,
-    relative 2-norm residual r2, relative forward error e (vs X_ref)."""
+def residual_columns(a, b, F, X, X_ref=None):
+    """Per right-hand side n (column of the [M][N] arrays), with
+    R = F - A X computed row by row from the matrix of section 2:
+        eta_n = |R_n|_inf / (|A|_inf |X_n|_inf + |F_n|_inf)   (normwise backward error),
+        r2_n  = |R_n|_2 / |F_n|_2                               (relative residual),
+        e_n   = |X_n - X_ref,n|_inf / |X_ref,n|_inf             (forward error, if X_ref).
+    Returns a dict of length-N arrays."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     F = np.asarray(F, dtype=np.float64)
     X = np.asarray(X, dtype=np.float64)
+    if F.ndim == 1:
+        F, X = F[:, None], X[:, None]
     R = F - b[:, None] * X
     if len(b) > 1:
         R[:-1] -= a[:, None] * X[1:]
@@ -285,11 +291,17 @@ def residual_metrics(a, b, F, X, X_ref=None):
     xinf = np.max(np.abs(X), axis=0)
     finf = np.max(np.abs(F), axis=0)
     rinf = np.max(np.abs(R), axis=0)
-    eta = rinf / np.maximum(normA * xinf + finf, 1e-300)
-    r2 = np.linalg.norm(R, axis=0) / np.maximum(np.linalg.norm(F, axis=0), 1e-300)
-    out = dict(eta=float(eta.max()), r2=float(r2.max()))
+    out = dict(eta=rinf / np.maximum(normA * xinf + finf, 1e-300),
+               r2=np.linalg.norm(R, axis=0) / np.maximum(np.linalg.norm(F, axis=0), 1e-300))
     if X_ref is not None:
         X_ref = np.asarray(X_ref, dtype=np.float64)
-        e = np.max(np.abs(X - X_ref), axis=0) / np.maximum(np.max(np.abs(X_ref), axis=0), 1e-300)
-        out["e"] = float(e.max())
+        if X_ref.ndim == 1:
+            X_ref = X_ref[:, None]
+        out["e"] = np.max(np.abs(X - X_ref), axis=0) / np.maximum(np.max(np.abs(X_ref), axis=0), 1e-300)
     return out
+
+
+def residual_metrics(a, b, F, X, X_ref=None):
+    """The maxima over the series of residual_columns' eta, r2 (and e)."""
+    cols = residual_columns(a, b, F, X, X_ref)
+    return {k: float(v.max()) for k, v in cols.items()}

@@ -224,6 +224,46 @@ def test_grad_matches_central_differences():
         assert abs(fd - gF[i, n]) <= 1e-7 * max(1.0, abs(fd))
 
 
+@pytest.mark.slow
+def test_grad_matches_central_differences_gradient_case():
+    # the differentiation workload at full size (M = 2048, N = 1024; the
+    # FP32 right-hand sides widened exactly): central differences with the
+    # absolute step h = 1e-6 on every a_i, every b_i and 64 seeded entries
+    # of F plus its two corners, each difference taken of the loss
+    # sum(W * X) through two full oracle solves of the perturbed series
+    w = wl.gradient_case()
+    a, b, W = w["a"], w["b"], w["W"]
+    F = w["F"].astype(np.float64)
+    M, N = F.shape
+    X = oracle.thomas(a, b, F)
+    gF, ga, gb = oracle.grad(a, b, X, W)
+    h = 1e-6
+
+    def fd(ap, bp, am, bm):
+        dX = oracle.thomas(ap, bp, F) - oracle.thomas(am, bm, F)
+        return float(np.sum(W * dX)) / (2 * h)
+
+    worst = 0.0
+    for i in range(M - 1):
+        d = np.zeros(M - 1); d[i] = h
+        g = fd(a + d, b, a - d, b)
+        worst = max(worst, abs(g - ga[i]) / max(1.0, abs(g)))
+    for i in range(M):
+        d = np.zeros(M); d[i] = h
+        g = fd(a, b + d, a, b - d)
+        worst = max(worst, abs(g - gb[i]) / max(1.0, abs(g)))
+    rng = np.random.default_rng(55)
+    cells = list(zip(rng.integers(0, M, 64), rng.integers(0, N, 64))) + [(0, 0), (M - 1, N - 1)]
+    for i, n in cells:
+        e = np.zeros(M); e[i] = h
+        # only column n of X depends on F[i, n]
+        dX = oracle.thomas(a, b, F[:, n] + e) - oracle.thomas(a, b, F[:, n] - e)
+        g = float(np.dot(W[:, n], dX)) / (2 * h)
+        worst = max(worst, abs(g - gF[i, n]) / max(1.0, abs(g)))
+    print(f"gradient case: max |fd - grad| / max(1, |fd|) = {worst:.3e}")
+    assert worst <= 1e-7
+
+
 def test_grad_self_adjoint_identity():
     rng = np.random.default_rng(22)
     M, N = 50, 3
@@ -233,6 +273,65 @@ def test_grad_self_adjoint_identity():
     X = oracle.thomas(a, b, F)
     gF, _, _ = oracle.grad(a, b, X, W)
     assert abs(np.sum(W * X) - np.sum(gF * F)) <= 1e-12 * np.sum(np.abs(W * X))
+
+
+# ------------------------------------------------------------------ residual metrics
+def _manufactured_residual_case():
+    # integer A (mixed-sign, non-constant off-diagonals, dominant diagonal)
+    # and integer X*: F0 = A X* is exact in FP64, and F = F0 + delta_n e_{k_n}
+    # with delta_n a power of two is exact too, so F - A X* is exactly
+    # delta_n e_{k_n} in column n: the residual is known in closed form.
+    rng = np.random.default_rng(41)
+    M, N = 57, 6
+    a = rng.integers(1, 4, size=M - 1) * rng.choice([-1.0, 1.0], size=M - 1)
+    b = (np.concatenate([[0], np.abs(a)]) + np.concatenate([np.abs(a), [0]]) + rng.integers(1, 3, size=M)).astype(np.float64)
+    Xs = rng.integers(-9, 10, size=(M, N)).astype(np.float64)
+    F = method.dense(a, b) @ Xs
+    rows = np.array([0, 1, 28, M - 2, M - 1, 13])
+    delta = np.array([2.0 ** -3, -(2.0 ** -7), 2.0 ** -20, -(2.0 ** 2), 2.0 ** -1, 2.0 ** -30])
+    F[rows, np.arange(N)] += delta
+    return a, b, Xs, F, rows, delta
+
+
+def test_residual_columns_manufactured_closed_form():
+    a, b, Xs, F, rows, delta = _manufactured_residual_case()
+    D = method.dense(a, b)
+    normA = np.abs(D).sum(axis=1).max()              # |A|_inf, max row sum
+    want_eta = np.abs(delta) / (normA * np.abs(Xs).max(axis=0) + np.abs(F).max(axis=0))
+    want_r2 = np.abs(delta) / np.sqrt((F ** 2).sum(axis=0))
+    got = method.residual_columns(a, b, F, Xs)
+    assert np.allclose(got["eta"], want_eta, rtol=1e-15, atol=0)
+    assert np.allclose(got["r2"], want_r2, rtol=1e-15, atol=0)
+    m = method.residual_metrics(a, b, F, Xs)
+    assert m["eta"] == want_eta.max() or abs(m["eta"] - want_eta.max()) <= 1e-15 * want_eta.max()
+    assert abs(m["r2"] - want_r2.max()) <= 1e-15 * want_r2.max()
+    # forward error against a reference with a known difference
+    X = Xs.copy()
+    X[rows, np.arange(len(rows))] += 0.5
+    e = method.residual_columns(a, b, F, X, Xs)["e"]
+    assert np.array_equal(e, 0.5 / np.abs(Xs).max(axis=0))
+
+
+def test_residual_columns_exact_solution_is_zero():
+    a, b, Xs, F, rows, delta = _manufactured_residual_case()
+    F0 = F.copy()
+    F0[rows, np.arange(len(rows))] -= delta
+    got = method.residual_columns(a, b, F0, Xs)
+    assert np.all(got["eta"] == 0.0) and np.all(got["r2"] == 0.0)
+
+
+def _residual_wrong_coupling(a, b, F, X):
+    # plausible slip: the upper neighbour's coupling applied to the row itself
+    R = F - b[:, None] * X
+    R[:-1] -= a[:, None] * X[:-1]
+    R[1:] -= a[:, None] * X[:-1]
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(F, axis=0)
+
+
+def test_planted_mistake_in_residual_is_caught():
+    a, b, Xs, F, rows, delta = _manufactured_residual_case()
+    want_r2 = np.abs(delta) / np.sqrt((F ** 2).sum(axis=0))
+    assert not np.allclose(_residual_wrong_coupling(a, b, F, Xs), want_r2, rtol=1e-6, atol=0)
 
 
 # ------------------------------------------------------------------ planted mistakes
