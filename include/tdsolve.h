@@ -210,6 +210,26 @@ int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
 enum { TDS_IFACE_RECURRENCE = 0, TDS_IFACE_DICHOTOMY = 1, TDS_IFACE_DENSE = 2 };
 int tdsolve_set_interface(tds_handle h, int32_t order);
 
+/* Fused order of the per-right-hand-side step for tdsolve_series of a
+ * single-matrix plan.  lag == 0 (default): three
+ * launches over the whole series (beta weights, interface values, block
+ * sweeps).  lag >= 1: one launch (after a small one that clears its
+ * counters) whose workgroups take the work items in ticket order, tile by
+ * tile of `tile` right-hand sides (a multiple of 256, at most 2^20): the
+ * beta weights of a tile, `lag` tiles later its interface values (each
+ * waits until the tile's weights are published), `lag` tiles later still
+ * its block sweeps (each waits for its tile's interface values only after
+ * its zero-boundary solves).  Reads of F
+ * for the weights overlap the writes of X, and the sweeps reread their F
+ * soon after the weights did.  Same work items and arithmetic as the three
+ * launches: bitwise the same X.  Taken when the plan sweeps its blocks in
+ * halves (tdsolve_info.sweep_halves), the mode has FP64 results, the order
+ * is the recurrence or the dense one, N is a multiple of 4 (FP32 input) or
+ * 2 (FP64 input) and F is 16-byte aligned; otherwise the three launches
+ * run.  Phase timing then reports the fused kernel as the sweep phase.
+ * Errors: TDS_EINVAL (batch handle, lag outside 0..64, a bad tile). */
+int tdsolve_set_fused(tds_handle h, int32_t lag, int32_t tile);
+
 /* Number of refinement passes for TDS_F32_REFINED (0..8; default 2). */
 int tdsolve_set_refinement(tds_handle h, int32_t passes);
 

@@ -27,6 +27,8 @@ struct tds_plan {
     int32_t iface = TDS_IFACE_RECURRENCE;   // interface-step evaluation order
     double* dense_K = nullptr;   // Theorem 2 coefficient table (TDS_IFACE_DENSE)
     int32_t dense_Pc = 0, dense_Mr = 0;
+    int32_t fuse_lag = 0;        // fused order: sweeps this many tiles behind (0: three kernels)
+    int32_t fuse_cols = 0;       // fused order: right-hand sides per tile
     int device = 0;
     void* work = nullptr;        // grows with N
     size_t work_bytes = 0;
@@ -245,22 +247,39 @@ struct Work {
     double* xsep;
     double* SR;
     double* SL;
+    int* sync;       // counters of the fused order (fused_sync_ints(N))
 };
 
-int take_work(tds_plan* h, int64_t N, Work& w) {
+// bytes of the work slices for N right-hand sides; nb, nx, ns: the slice sizes
+size_t work_bytes(const tds_plan* h, int64_t N, size_t* nb_, size_t* nx_, size_t* ns_) {
     const size_t P = (size_t)h->dev.P;
     const size_t nb = align256(sizeof(double) * P * (size_t)N);
     const size_t nx = align256(sizeof(double) * (P > 1 ? P - 1 : 1) * (size_t)N);
     const size_t ns = (h->iface == TDS_IFACE_DICHOTOMY)
                           ? align256(sizeof(double) * (P + 1) * (size_t)N) : 0;
-    const int rc = ensure_work(h, 2 * nb + nx + 2 * ns);
-    if (rc) return rc;
-    char* base = general_of(h);
+    const size_t nc = align256(sizeof(int) * (size_t)fused_sync_ints(N));
+    if (nb_) *nb_ = nb;
+    if (nx_) *nx_ = nx;
+    if (ns_) *ns_ = ns;
+    return 2 * nb + nx + 2 * ns + nc;
+}
+
+// the slices laid out from `base`
+void carve_work(const tds_plan* h, int64_t N, char* base, Work& w) {
+    size_t nb, nx, ns;
+    (void)work_bytes(h, N, &nb, &nx, &ns);
     w.betaR = (double*)base;
     w.betaL = (double*)(base + nb);
     w.xsep = (double*)(base + 2 * nb);
     w.SR = ns ? (double*)(base + 2 * nb + nx) : nullptr;
     w.SL = ns ? (double*)(base + 2 * nb + nx + ns) : nullptr;
+    w.sync = (int*)(base + 2 * nb + nx + 2 * ns);
+}
+
+int take_work(tds_plan* h, int64_t N, Work& w) {
+    const int rc = ensure_work(h, work_bytes(h, N, nullptr, nullptr, nullptr));
+    if (rc) return rc;
+    carve_work(h, N, general_of(h), w);
     return TDS_OK;
 }
 
@@ -297,15 +316,36 @@ KTime* timing_slot(tds_plan* h) {
 // unrecorded and it reads as zero
 void empty_phase(tds_plan* h, int k) { h->timed_empty.back() |= (uint8_t)(1u << k); }
 
+// `given` (may be null): work slices supplied by the caller (the entry point
+// that allocates nothing); then the call neither grows the plan's work
+// buffer nor records phase timing
 int series_impl(tds_plan* h, const void* F, void* X, int64_t N, int32_t mode, hipStream_t s,
-                int sweep_mode) {
+                int sweep_mode, const Work* given = nullptr) {
     const DevTables& t = h->dev;
     Work w;
-    int rc = take_work(h, N, w);
-    if (rc) return rc;
+    if (given) {
+        w = *given;
+    } else {
+        const int rc = take_work(h, N, w);
+        if (rc) return rc;
+    }
     double* xsep = w.xsep;
-    KTime* tm = timing_slot(h);
-    if (h->timing && !tm) return TDS_EHIP;
+    KTime* tm = given ? nullptr : timing_slot(h);
+    if (h->timing && !given && !tm) return TDS_EHIP;
+    if (h->fuse_lag > 0 && fused_fits(t, h->has_halves ? &h->halves : nullptr, F, N,
+                                      sweep_mode, h->iface)) {
+        // the whole solve as one fused launch (timed as the sweep phase)
+        if (tm) {
+            empty_phase(h, 0);
+            empty_phase(h, 1);
+        }
+        const bool dense = h->iface == TDS_IFACE_DENSE;
+        if (launch_fused(t, h->halves, F, X, N, sweep_mode, h->passes, w.betaR, w.betaL, xsep,
+                         dense ? h->dense_K : nullptr, h->dense_Pc, h->dense_Mr, h->fuse_lag,
+                         h->fuse_cols, w.sync, s, tm ? tm + 2 : nullptr) != hipSuccess)
+            return TDS_EHIP;
+        return TDS_OK;
+    }
     if (t.P >= 2 && N > 0) {
         if (launch_beta(t, F, mode != TDS_F64, N, w.betaR, w.betaL, s, tm) != hipSuccess)
             return TDS_EHIP;
@@ -364,6 +404,8 @@ void remember(tds_plan* h, const void* const* F, void* const* X, const int64_t* 
     h->last_passes = mode == TDS_F32_REFINED ? h->passes : 0;
     h->have_last = true;
 }
+
+constexpr int32_t kFuseMaxLag = 64;
 
 }  // namespace
 
@@ -545,6 +587,14 @@ int tdsolve_set_interface(tds_handle h, int32_t order) {
         h->dense_Mr = mr;
     }
     h->iface = order;
+    return TDS_OK;
+}
+
+int tdsolve_set_fused(tds_handle h, int32_t lag, int32_t tile) {
+    if (!h || h->is_batch || lag < 0 || lag > kFuseMaxLag) return TDS_EINVAL;
+    if (lag > 0 && (tile < 256 || tile % 256 != 0 || tile > (1 << 20))) return TDS_EINVAL;
+    h->fuse_lag = lag;
+    h->fuse_cols = lag > 0 ? tile : 0;
     return TDS_OK;
 }
 

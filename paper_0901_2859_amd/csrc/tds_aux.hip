@@ -67,45 +67,67 @@ __global__ __launch_bounds__(kWG) void k_resid_finish(const double* __restrict__
 }
 
 // --------------------------------------------------------------------------
-// Adjoint reductions over the series: one workgroup per row i, a fixed
-// strided order per lane and a fixed LDS tree, so results are bitwise
-// reproducible (no floating-point atomics).  g32 (may be null) receives
-// row i of gF rounded to FP32 on the way.
+// Adjoint reductions over the series: one workgroup per kAdjRows rows
+// i0 .. i0 + kAdjRows - 1, which reads rows i0 .. i0 + kAdjRows of X and gF
+// once each (row i + 1 serves both ga_i and gb_{i+1}), so the kernel moves
+// (1 + 1 / kAdjRows) times the bytes of X and gF.  Every lane sums its
+// right-hand sides n = lane, lane + 256, ... in that order, then a fixed LDS
+// tree adds the lanes: results are bitwise reproducible (no floating-point
+// atomics).  g32 (may be null) receives rows of gF rounded to FP32 on the
+// way.
+constexpr int kAdjRows = 4;
+
 template <typename Xin, typename Gin>
 __global__ __launch_bounds__(kWG) void k_adjoint_reduce(const Xin* __restrict__ X,
                                                         const Gin* __restrict__ gF, int64_t N,
                                                         int64_t M, float* __restrict__ g32,
                                                         double* __restrict__ ga,
                                                         double* __restrict__ gb) {
-    __shared__ double sa[kWG], sb[kWG];
-    const int64_t i = blockIdx.x;
-    double accb = 0.0, acca = 0.0;
-    const bool has_next = (i + 1 < M);
+    __shared__ double sa[kAdjRows][kWG], sb[kAdjRows][kWG];
+    const int64_t i0 = (int64_t)blockIdx.x * kAdjRows;
+    const int rows = (int)min<int64_t>(kAdjRows, M - i0);       // rows reduced here
+    double acca[kAdjRows], accb[kAdjRows];
+#pragma unroll
+    for (int r = 0; r < kAdjRows; ++r) acca[r] = accb[r] = 0.0;
     for (int64_t n = threadIdx.x; n < N; n += kWG) {
-        const double x = (double)X[i * N + n];
-        const double g = (double)gF[i * N + n];
-        if (g32) g32[i * N + n] = (float)g;
-        accb = fma(g, x, accb);
-        if (has_next) {
-            const double x1 = (double)X[(i + 1) * N + n];
-            const double g1 = (double)gF[(i + 1) * N + n];
-            acca = fma(g, x1, acca);
-            acca = fma(g1, x, acca);
+        double x[kAdjRows + 1], g[kAdjRows + 1];
+#pragma unroll
+        for (int r = 0; r <= kAdjRows; ++r) {
+            // rows past the matrix (and row i0 + kAdjRows past M) are zero
+            const bool in = r < rows || (r == rows && i0 + r < M);
+            x[r] = in ? (double)X[(i0 + r) * N + n] : 0.0;
+            g[r] = in ? (double)gF[(i0 + r) * N + n] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kAdjRows; ++r) {
+            if (r < rows) {
+                if (g32) g32[(i0 + r) * N + n] = (float)g[r];
+                accb[r] = fma(g[r], x[r], accb[r]);
+                acca[r] = fma(g[r], x[r + 1], acca[r]);
+                acca[r] = fma(g[r + 1], x[r], acca[r]);
+            }
         }
     }
-    sa[threadIdx.x] = acca;
-    sb[threadIdx.x] = accb;
+#pragma unroll
+    for (int r = 0; r < kAdjRows; ++r) {
+        sa[r][threadIdx.x] = acca[r];
+        sb[r][threadIdx.x] = accb[r];
+    }
     __syncthreads();
     for (int w = kWG / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            sa[threadIdx.x] += sa[threadIdx.x + w];
-            sb[threadIdx.x] += sb[threadIdx.x + w];
+#pragma unroll
+            for (int r = 0; r < kAdjRows; ++r) {
+                sa[r][threadIdx.x] += sa[r][threadIdx.x + w];
+                sb[r][threadIdx.x] += sb[r][threadIdx.x + w];
+            }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        if (gb) gb[i] = -sb[0];
-        if (ga && has_next) ga[i] = -sa[0];
+    if (threadIdx.x < rows) {
+        const int64_t i = i0 + threadIdx.x;
+        if (gb) gb[i] = -sb[threadIdx.x][0];
+        if (ga && i + 1 < M) ga[i] = -sa[threadIdx.x][0];
     }
 }
 
@@ -173,7 +195,7 @@ hipError_t launch_adjoint_reduce(const DevTables& t, const void* X, const void* 
                                  bool f32g, int64_t N, float* g32, double* ga, double* gb,
                                  hipStream_t s) {
     if (N == 0 || (!ga && !gb && !g32)) return hipSuccess;
-    dim3 g((unsigned)t.M, 1, 1);
+    dim3 g((unsigned)((t.M + kAdjRows - 1) / kAdjRows), 1, 1);
     if (!f32x && !f32g)
         hipLaunchKernelGGL((k_adjoint_reduce<double, double>), g, dim3(kWG), 0, s,
                            (const double*)X, (const double*)gF, N, t.M, g32, ga, gb);

@@ -133,7 +133,23 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
                         hipStream_t s, const KTime* tm = nullptr,
                         const DevTables* halves = nullptr);
 
-// register-sweep row bucket (32, 64, 128) of a largest block size, 0 if the
+// Fused solve (k_fused): beta weights, interface step and block sweeps in
+// one launch over tiles of W right-hand sides (a multiple of 256), the
+// sweeps of a tile `lag` stages (tiles) after its weights (lag >= 1).  Needs the half-block tables
+// h (blocks of 33..64 rows), FP64 results, the recurrence order (Kt null) or
+// the dense one (Kt, Pc, Mr as for launch_iface_dense), N a multiple of 4
+// (FP32 input) or 2 (FP64) and F 16-byte aligned (fused_fits); sync: device
+// ints, fused_sync_ints(N) of them, zeroed by the launcher.  `tm` times the
+// fused kernel.
+bool fused_fits(const DevTables& t, const DevTables* halves, const void* F, int64_t N, int mode,
+                int order);
+int64_t fused_sync_ints(int64_t N);
+hipError_t launch_fused(const DevTables& t, const DevTables& h, const void* F, void* X,
+                        int64_t N, int mode, int passes, double* betaR, double* betaL,
+                        double* xsep, const double* Kt, int32_t Pc, int32_t Mr, int32_t lag,
+                        int32_t W, int* sync, hipStream_t s, const KTime* tm = nullptr);
+
+// register-sweep row bucket (32, 64, 128)// register-sweep row bucket (32, 64, 128) of a largest block size, 0 if the
 // streaming sweep is needed
 int32_t rows_bucket(int32_t max_rows);
 // shape of the two-level interface scan: blocks per group, groups

@@ -70,6 +70,29 @@ __device__ __forceinline__ void store_x(T* p, T v) {
     __builtin_nontemporal_store(v, p);
 }
 
+// Work-area values (beta weights, interface values) that workgroups of one
+// launch hand to each other (the fused order, k_fused) are written through
+// to, and read back from, the device-wide coherence point: agent-scope
+// relaxed atomic accesses, which gfx950 issues as global stores and loads
+// with the sc1 bit.  Each XCD's L2 is not coherent with the other XCDs', so
+// ordinary accesses could leave a value in one L2 or read a stale line from
+// another.  COH = false: ordinary accesses (values handed over between
+// launches, where the kernel boundary makes them visible).
+template <bool COH>
+__device__ __forceinline__ double ld_w(const double* p) {
+    if constexpr (COH)
+        return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void st_w(double* p, double v) {
+    if constexpr (COH)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
 // ==========================================================================
 // beta weights (eq. beta_symn).  Item (tile, j): block j of rows x 64
 // consecutive right-hand sides (one per lane); the four wavefronts of the
@@ -174,7 +197,7 @@ struct Vec16<double> {
     using type = double2;
 };
 
-template <int TMAX, typename Fin>
+template <int TMAX, typename Fin, bool COH = false>
 __device__ __forceinline__ void beta_item_vec(const DevTables& T, const Fin* __restrict__ F,
                                               int64_t N, int32_t j, int64_t tile,
                                               double* __restrict__ betaR,
@@ -233,8 +256,8 @@ __device__ __forceinline__ void beta_item_vec(const DevTables& T, const Fin* __r
         double* oL = &betaL[(int64_t)j * N + n0 + V * lane];
 #pragma unroll
         for (int q = 0; q < V; ++q) {
-            if (j < T.P - 1) oR[q] = bR[q];
-            if (j > 0) oL[q] = bL[q];
+            if (j < T.P - 1) st_w<COH>(&oR[q], bR[q]);
+            if (j > 0) st_w<COH>(&oL[q], bL[q]);
         }
     }
 }
@@ -313,6 +336,7 @@ constexpr int kChainChunk = 8;     // beta values read per memory round trip
 // S^R recurrence y <- rho_j y + beta^R_j for j = j0 .. j1-1 (rho_0 is not
 // used: S^R_0 = 0), reading kChainChunk values per round trip; every y is
 // stored to out[j] when out is given.
+template <bool COH = false>
 __device__ __forceinline__ double chain_right(double y, const cptr<double> rho,
                                               const double* __restrict__ beta, int64_t N,
                                               int64_t n, int32_t j0, int32_t j1,
@@ -321,13 +345,13 @@ __device__ __forceinline__ double chain_right(double y, const cptr<double> rho,
         double v[kChainChunk];
 #pragma unroll
         for (int u = 0; u < kChainChunk; ++u)
-            v[u] = (jb + u < j1) ? beta[(int64_t)(jb + u) * N + n] : 0.0;
+            v[u] = (jb + u < j1) ? ld_w<COH>(&beta[(int64_t)(jb + u) * N + n]) : 0.0;
 #pragma unroll
         for (int u = 0; u < kChainChunk; ++u) {
             const int32_t j = jb + u;
             if (j < j1) {
                 y = fma((j > 0) ? rho[j] : 0.0, y, v[u]);
-                if (out) out[(int64_t)j * N + n] = y;
+                if (out) st_w<COH>(&out[(int64_t)j * N + n], y);
             }
         }
     }
@@ -336,6 +360,7 @@ __device__ __forceinline__ double chain_right(double y, const cptr<double> rho,
 
 // S^L recurrence z <- beta^L_j + lam_j z for j = j1 down to j0+1 (lam_{P-1}
 // is not used: S^L_P = 0); with out given, z is added to out[j-1].
+template <bool COH = false>
 __device__ __forceinline__ double chain_left(double z, const cptr<double> lam, int32_t P,
                                              const double* __restrict__ beta, int64_t N,
                                              int64_t n, int32_t j1, int32_t j0,
@@ -344,13 +369,16 @@ __device__ __forceinline__ double chain_left(double z, const cptr<double> lam, i
         double v[kChainChunk];
 #pragma unroll
         for (int u = 0; u < kChainChunk; ++u)
-            v[u] = (jb - u > j0) ? beta[(int64_t)(jb - u) * N + n] : 0.0;
+            v[u] = (jb - u > j0) ? ld_w<COH>(&beta[(int64_t)(jb - u) * N + n]) : 0.0;
 #pragma unroll
         for (int u = 0; u < kChainChunk; ++u) {
             const int32_t j = jb - u;
             if (j > j0) {
                 z = fma((j < P - 1) ? lam[j] : 0.0, z, v[u]);
-                if (out) out[(int64_t)(j - 1) * N + n] += z;
+                if (out) {
+                    double* o = &out[(int64_t)(j - 1) * N + n];
+                    st_w<COH>(o, ld_w<COH>(o) + z);
+                }
             }
         }
     }
@@ -366,7 +394,7 @@ __host__ __device__ constexpr size_t scan_lds_doubles(int32_t G, int32_t per,
     return (size_t)2 * G * R + 2 * G + (per <= maxper ? (size_t)G * per * R : 0);
 }
 
-template <int MAXPER>
+template <int MAXPER, bool COH = false>
 __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_t per,
                                            int32_t G, const double* __restrict__ betaR,
                                            const double* __restrict__ betaL,
@@ -398,8 +426,8 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
 #pragma unroll
             for (int u = 0; u < MAXPER; ++u) {
                 const int32_t jf = f0 + u, jb = b1 - u;
-                bRv[u] = (jf < f1) ? betaR[(int64_t)jf * N + n] : 0.0;
-                bLv[u] = (jb > b0) ? betaL[(int64_t)jb * N + n] : 0.0;
+                bRv[u] = (jf < f1) ? ld_w<COH>(&betaR[(int64_t)jf * N + n]) : 0.0;
+                bLv[u] = (jb > b0) ? ld_w<COH>(&betaL[(int64_t)jb * N + n]) : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < MAXPER; ++u) {
@@ -408,8 +436,8 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
                 if (jb > b0) zl = fma((jb < P - 1) ? lam[jb] : 0.0, zl, bLv[u]);
             }
         } else {
-            yl = chain_right(yl, rho, betaR, N, n, f0, f1, nullptr);
-            zl = chain_left(zl, lam, P, betaL, N, n, b1, b0, nullptr);
+            yl = chain_right<COH>(yl, rho, betaR, N, n, f0, f1, nullptr);
+            zl = chain_left<COH>(zl, lam, P, betaL, N, n, b1, b0, nullptr);
         }
     }
     double* carry = smem;                              // [2][G][R]
@@ -442,7 +470,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
                 }
             }
         } else {
-            chain_right(y, rho, betaR, N, n, f0, f1, xsep);
+            chain_right<COH>(y, rho, betaR, N, n, f0, f1, xsep);
         }
     }
     __syncthreads();     // S^R of every group is in LDS or xsep (same workgroup)
@@ -454,11 +482,11 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             const int32_t j = b1 - u;
             if (j > b0) {
                 z = fma((j < P - 1) ? lam[j] : 0.0, z, bLv[u]);
-                xsep[(int64_t)(j - 1) * N + n] = sr[(j - 1) * R + lane] + z;   // S^R_j + S^L_j
+                st_w<COH>(&xsep[(int64_t)(j - 1) * N + n], sr[(j - 1) * R + lane] + z);   // S^R_j + S^L_j
             }
         }
     } else {
-        chain_left(z, lam, P, betaL, N, n, b1, b0, xsep);   // x(s_j) = S^R_j + S^L_j
+        chain_left<COH>(z, lam, P, betaL, N, n, b1, b0, xsep);   // x(s_j) = S^R_j + S^L_j
     }
 }
 
@@ -542,17 +570,20 @@ constexpr int kDenseCols = 16;      // right-hand sides per workgroup
 constexpr int kDenseRows = 64;      // output rows per workgroup (4 tiles)
 constexpr int kDenseBatch = 32;     // k-steps whose operands are loaded together
 
-__global__ __launch_bounds__(kWG) void k_iface_dense(const double* __restrict__ Kt, int32_t Pc,
-                                                     int32_t Mr, int32_t P, int64_t N,
-                                                     const double* __restrict__ betaR,
-                                                     const double* __restrict__ betaL,
-                                                     double* __restrict__ xsep) {
+// one workgroup's share of the dense product: output rows by * kDenseRows
+// .. + 63 (one 16-row tile per wavefront) x right-hand sides bx *
+// kDenseCols .. + 15; BATCH k-steps have their operands loaded at once
+template <int BATCH, bool COH = false>
+__device__ __forceinline__ void dense_item(const double* __restrict__ Kt, int32_t Pc, int32_t Mr,
+                                           int32_t P, int64_t N, const double* __restrict__ betaR,
+                                           const double* __restrict__ betaL,
+                                           double* __restrict__ xsep, int64_t bx, int32_t by) {
     using d4 = __attribute__((ext_vector_type(4))) double;
     const int lane = threadIdx.x % 64;
     const int tile = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int col = lane % 16, kq = lane / 16;
-    const int64_t n = (int64_t)blockIdx.x * kDenseCols + col;
-    const int32_t rlo = (int32_t)blockIdx.y * kDenseRows + 16 * tile;
+    const int64_t n = bx * kDenseCols + col;
+    const int32_t rlo = by * kDenseRows + 16 * tile;
     if (rlo >= P - 1) return;                      // tile past the last interface row
     const int32_t rhi = min(rlo + 15, P - 2);
     // steps: right part j4 = 0, 4, .., <= rhi; left part j4 = (rlo + 1) & ~3, .., <= P-1
@@ -562,28 +593,43 @@ __global__ __launch_bounds__(kWG) void k_iface_dense(const double* __restrict__ 
     const int32_t steps = nR + nL;
     const bool live = n < N;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t s0 = 0; s0 < steps; s0 += kDenseBatch) {
-        double av[kDenseBatch], bv[kDenseBatch];
+    for (int32_t s0 = 0; s0 < steps; s0 += BATCH) {
+        double av[BATCH], bv[BATCH];
 #pragma unroll
-        for (int u = 0; u < kDenseBatch; ++u) {
+        for (int u = 0; u < BATCH; ++u) {
             const int32_t st = s0 + u;
             const bool left = st >= nR;
             const int32_t j = left ? jl0 + 4 * (st - nR) + kq : 4 * st + kq;
             const int32_t kk = left ? Pc + j : j;
             const bool ok = st < steps && j < P;
+            // the step's four j can reach past the weights this tile uses
+            // (beta^R_j for j <= rhi, beta^L_j for j > rlo); those rows of
+            // the work area (beta^R_{P-1}, beta^L_0 among them) are never
+            // written, so they are not read either: their coefficients are
+            // zero, but 0 times a stale non-finite value is not
+            const bool need = left ? (j > rlo) : (j <= rhi);
             av[u] = ok ? Kt[(int64_t)kk * Mr + rlo + col] : 0.0;
-            bv[u] = (ok && live) ? (left ? betaL : betaR)[(int64_t)j * N + n] : 0.0;
+            bv[u] = (ok && live && need) ? ld_w<COH>(&(left ? betaL : betaR)[(int64_t)j * N + n]) : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kDenseBatch; ++u)
+        for (int u = 0; u < BATCH; ++u)
             if (s0 + u < steps) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
     if (!live) return;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int32_t r = rlo + 4 * i + kq;
-        if (r < P - 1) xsep[(int64_t)r * N + n] = acc[i];
+        if (r < P - 1) st_w<COH>(&xsep[(int64_t)r * N + n], acc[i]);
     }
+}
+
+__global__ __launch_bounds__(kWG) void k_iface_dense(const double* __restrict__ Kt, int32_t Pc,
+                                                     int32_t Mr, int32_t P, int64_t N,
+                                                     const double* __restrict__ betaR,
+                                                     const double* __restrict__ betaL,
+                                                     double* __restrict__ xsep) {
+    dense_item<kDenseBatch>(Kt, Pc, Mr, P, N, betaR, betaL, xsep, (int64_t)blockIdx.x,
+                            (int32_t)blockIdx.y);
 }
 
 // ==========================================================================
@@ -889,11 +935,23 @@ constexpr uint32_t kXcdsSweep = 8;   // XCDs of the chip (workgroups dispatched 
 // kSweepRefined (FP32 input, refined_solve; s_f: kHalfRows x 2 RHS floats of
 // LDS) or kSweep64 (FP64 arithmetic on FP32 or FP64 input, no refinement;
 // s_f unused).  s_q: 2 RHS doubles of LDS.
-template <int RHS, typename Fin, int KIND, bool GEN>
+// The item's two interface values are read before its loads of F, or, with
+// a Wait functor whose kFused is true (the fused order), only after the
+// zero-boundary solves and a call of wait(), which returns once the
+// interface step of these right-hand sides has finished; they are then read
+// from the coherence point.
+struct NoWait {
+    static constexpr bool kFused = false;
+    __device__ bool ready() const { return true; }
+    __device__ void operator()() const {}
+};
+
+template <int RHS, typename Fin, int KIND, bool GEN, typename Wait = NoWait>
 __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __restrict__ F,
                                             double* __restrict__ X, int64_t N, int32_t j,
                                             int64_t tile, const double* __restrict__ xsep,
-                                            int passes, float* s_f, double* s_q) {
+                                            int passes, float* s_f, double* s_q,
+                                            Wait wait = Wait()) {
     constexpr int TM = kHalfRows, NT = 2 * RHS;
     const int32_t P = H.P >> 1;                 // blocks of the method's partition
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / RHS);   // 0 left, 1 right
@@ -908,8 +966,19 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
     const int cnt = (int)(seg_hi - i0);         // TM on the left, 1..TM on the right
     // the block's outer boundary value on this half's side
     double xo = 0.0;
-    if (h == 0 && j > 0) xo = xsep[(int64_t)(j - 1) * N + n0 + lane];
-    if (h == 1 && j < P - 1) xo = xsep[(int64_t)j * N + n0 + lane];
+    bool early = true;
+    if constexpr (Wait::kFused) {
+        // the interface values are usually published long before: then they
+        // are read here, beside the loads of F, as in the three-launch order
+        early = wait.ready();
+        if (early) {
+            if (h == 0 && j > 0) xo = ld_w<true>(&xsep[(int64_t)(j - 1) * N + n0 + lane]);
+            if (h == 1 && j < P - 1) xo = ld_w<true>(&xsep[(int64_t)j * N + n0 + lane]);
+        }
+    } else {
+        if (h == 0 && j > 0) xo = xsep[(int64_t)(j - 1) * N + n0 + lane];
+        if (h == 1 && j < P - 1) xo = xsep[(int64_t)j * N + n0 + lane];
+    }
     Fin f[TM];
     sweep_load<TM, Fin>(F + i0 * N + n0, lane, N, cnt, f);
     double fm = 0.0;
@@ -933,6 +1002,13 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
         }
 #pragma unroll
         for (int r = TM - 2; r >= 0; --r) x[r] -= cp64[r] * x[r + 1];
+    }
+    if constexpr (Wait::kFused) {
+        if (!__syncthreads_and(early)) {         // one decision for the workgroup
+            wait();
+            if (h == 0 && j > 0) xo = ld_w<true>(&xsep[(int64_t)(j - 1) * N + n0 + lane]);
+            if (h == 1 && j < P - 1) xo = ld_w<true>(&xsep[(int64_t)j * N + n0 + lane]);
+        }
     }
     const cptr<double> uu = cst(H.u + i0), vv = cst(H.v + i0);
     if (h == 0)
@@ -991,6 +1067,203 @@ __global__ __launch_bounds__(kWG) void k_sweep_stream(DevTables T, const Fin* __
 }
 
 // ==========================================================================
+// Fused solve of one matrix whose blocks the sweeps take in halves: the beta
+// weights, the interface step and the block sweeps in one launch, with no
+// kernel boundary between them.  The series is cut into tiles of kFuseCols
+// right-hand sides; tile tau has
+//   nb beta items (P blocks x the beta tiles of 64 V columns it holds),
+//   ni interface items (dense: column tiles of kDenseCols x row tiles;
+//      recurrence: groups of 2^lgR columns, the groups of k_iface),
+//   ns = 2 P sweep items (P blocks x two tiles of kHalfRhs columns).
+// Every workgroup takes a ticket (one atomic increment) and runs the item the
+// ticket names.  Stage s holds, in this order, the interface items of tile
+// s - LI, the sweep items of tile s - LS and the beta items of tile s
+// (LS = 2 LI, LI = the lag): the beta pass of a tile runs LS stages ahead of its sweeps,
+// so the sweeps find its F rows still in a cache and its interface values
+// long computed, and reads of F for the weights overlap writes of X.
+//
+// An interface item waits until the nb beta items of its tile have
+// published their weights; a sweep item first solves its halves with zero
+// boundary values (the work that does not need the interface values) and
+// only then waits until the ni interface items of its tile have published
+// theirs.  Every wait is on items with smaller tickets: those have started
+// (running workgroups take tickets in increasing order) and never wait on a
+// larger ticket, so the item of the smallest unfinished ticket can always
+// progress and the launch cannot deadlock, however many workgroups are
+// resident.  Each wait is bounded all the same (kSpinLimit polls; past it
+// the error word is set and the item goes on).  Publishing: the values are
+// written through to the device's coherence point (st_w<true>), every wave
+// waits for its stores to complete, then one thread increments the tile's
+// counter; consumers poll the counter and read with ld_w<true>.  The items
+// and their arithmetic are those of k_beta_vec, k_iface / k_iface_dense and
+// k_sweep_halves, so X is bitwise that of the three-launch order.
+constexpr int64_t kFuseCols = 256;
+constexpr int kSpinLimit = 1 << 22;
+// every counter of the fused order sits on a line of its own, so that the
+// ticket increments, the tile counters' increments and the polls of waiting
+// workgroups do not contend for one cache line
+constexpr int kSyncStride = 64;   // ints (256 bytes)
+
+struct FuseShape {
+    int64_t T;           // tiles of W right-hand sides
+    int32_t W;           // right-hand sides per tile (a multiple of kFuseCols)
+    int32_t LI, LS;      // stage lags of the interface and sweep items
+    int32_t nb, ni, ns;  // items per tile
+    int32_t rowtiles;    // dense row tiles (1: recurrence order)
+    int32_t bpt;         // beta tiles per fuse tile
+    int32_t spt;         // sweep tiles (kHalfRhs columns) per fuse tile
+};
+
+__device__ __forceinline__ int64_t fuse_stage_size(const FuseShape& f, int64_t s) {
+    int64_t z = 0;
+    if (s >= f.LI && s - f.LI < f.T) z += f.ni;
+    if (s >= f.LS && s - f.LS < f.T) z += f.ns;
+    if (s < f.T) z += f.nb;
+    return z;
+}
+
+// wait until *cnt >= target (thread 0 polls; the workgroup then proceeds)
+__device__ __forceinline__ void fuse_wait(const int* cnt, int target, int* err) {
+    if (threadIdx.x == 0) {
+        int polls = 0;
+        while (__hip_atomic_load(const_cast<int*>(cnt), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++polls > kSpinLimit) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    __syncthreads();
+}
+
+// publish: every wave's stores have completed, then one increment
+__device__ __forceinline__ void fuse_signal(int* cnt) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct FuseWait {
+    static constexpr bool kFused = true;
+    const int* cnt;
+    int target;
+    int* err;
+    // one look at the counter, no wait (every lane loads the same word)
+    __device__ bool ready() const {
+        return __hip_atomic_load(const_cast<int*>(cnt), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) >= target;
+    }
+    __device__ void operator()() const { fuse_wait(cnt, target, err); }
+};
+
+// LDS of a fused workgroup (doubles): the largest of the halves sweep
+// (refined: kHalfRows x 2 kHalfRhs floats of F, then 2 kHalfRhs doubles;
+// FP64 arithmetic: the 2 kHalfRhs doubles only), the beta reduction and the
+// 256-thread interface scan
+constexpr int kFuseSweepLds = kHalfRows * kHalfRhs + 2 * kHalfRhs;
+constexpr int kFuseSweep64Lds = 2 * kHalfRhs;
+constexpr int kFuseScanLds = 2 * kScanBatchThreads + 2 * kScanMaxGroupsSingle +
+                             kScanBatchThreads * kScanMaxPer;
+constexpr int kFuseBetaLds = 2 * (kBetaWaves - 1) * 4 * kBetaRhs;
+constexpr int kFuseDenseBatch = 16;   // k-steps per operand load (register budget)
+
+// sync: lines (kSyncStride ints) of [0] the ticket, [1] the error word,
+// [2, 2 + T) the beta counters, [2 + T, 2 + 2T) the interface counters;
+// zero before the launch
+template <typename Fin, int KIND, bool DENSE, bool GEN>
+__global__ __launch_bounds__(2 * kHalfRhs, 4) void k_fused(
+    DevTables T, DevTables H, const Fin* __restrict__ F, double* __restrict__ X, int64_t N,
+    double* betaR, double* betaL, double* xsep, const double* __restrict__ Kt, int32_t Pc,
+    int32_t Mr, int32_t per, int32_t G, int32_t lgR, int passes, FuseShape fs, int* sync) {
+    static_assert(2 * kHalfRhs == kWG, "one workgroup shape for every item");
+    constexpr int LS = KIND == kSweepRefined ? kFuseSweepLds : kFuseSweep64Lds;
+    constexpr int L0 = LS > kFuseBetaLds ? LS : kFuseBetaLds;
+    constexpr int LDS = DENSE ? L0 : (L0 > kFuseScanLds ? L0 : kFuseScanLds);
+    __shared__ double smem[LDS];
+    __shared__ int64_t s_ticket;
+    if (threadIdx.x == 0)
+        s_ticket = __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    int64_t rem = s_ticket;
+    int* err = sync + kSyncStride;
+    int* beta_done = sync + 2 * kSyncStride;                  // line 2 + tau
+    int* iface_done = sync + (2 + fs.T) * kSyncStride;        // line 2 + T + tau
+    // ticket -> (stage, index in stage): stage sizes are constant between
+    // the breakpoints 0, LI, LS, T, T + LI, T + LS
+    int64_t bp[6] = {0, fs.LI, fs.LS, fs.T, fs.T + fs.LI, fs.T + fs.LS};
+    for (int a = 1; a < 6; ++a)
+        for (int b = a; b > 0 && bp[b - 1] > bp[b]; --b) {
+            const int64_t tmp = bp[b];
+            bp[b] = bp[b - 1];
+            bp[b - 1] = tmp;
+        }
+    int64_t stage = -1, idx = 0;
+    for (int k = 0; k < 5 && stage < 0; ++k) {
+        const int64_t lo = bp[k], hi = bp[k + 1];
+        if (hi <= lo) continue;
+        const int64_t sz = fuse_stage_size(fs, lo);
+        if (sz == 0) continue;
+        if (rem < (hi - lo) * sz) {
+            stage = lo + rem / sz;
+            idx = rem % sz;
+        } else {
+            rem -= (hi - lo) * sz;
+        }
+    }
+    if (stage < 0) return;                       // past the last item (not launched)
+    const int32_t P = T.P;
+    // interface items of tile stage - LI
+    if (stage >= fs.LI && stage - fs.LI < fs.T) {
+        if (idx < fs.ni) {
+            const int64_t tau = stage - fs.LI;
+            fuse_wait(beta_done + tau * kSyncStride, fs.nb, err);
+            if constexpr (DENSE) {
+                const int64_t ct = tau * (fs.W / kDenseCols) + idx / fs.rowtiles;
+                dense_item<kFuseDenseBatch, true>(Kt, Pc, Mr, P, N, betaR, betaL, xsep, ct,
+                                                  (int32_t)(idx % fs.rowtiles));
+            } else {
+                const int64_t sblk = ((tau * fs.W) >> lgR) + idx;
+                iface_item<kScanMaxPer, true>(T, N, per, G, betaR, betaL, xsep, sblk, smem, lgR);
+            }
+            fuse_signal(iface_done + tau * kSyncStride);
+            return;
+        }
+        idx -= fs.ni;
+    }
+    // sweep items of tile stage - LS: block-major, neighbouring column
+    // tiles of one block next to each other (consecutive workgroups read
+    // and write adjacent spans of the same rows)
+    if (stage >= fs.LS && stage - fs.LS < fs.T) {
+        if (idx < fs.ns) {
+            const int64_t tau = stage - fs.LS;
+            const int64_t ht = tau * fs.spt + idx % fs.spt;     // tile of kHalfRhs columns
+            if (ht * kHalfRhs >= N) return;
+            FuseWait w{iface_done + tau * kSyncStride, fs.ni, err};
+            halves_item<kHalfRhs, Fin, KIND, GEN, FuseWait>(
+                H, F, X, N, (int32_t)(idx / fs.spt), ht, xsep, passes, (float*)smem,
+                KIND == kSweepRefined ? smem + kHalfRows * kHalfRhs : smem, w);
+            return;
+        }
+        idx -= fs.ns;
+    }
+    // beta items of tile stage, block-major as the sweeps
+    {
+        const int64_t tau = stage;
+        const int64_t bt = tau * fs.bpt + idx % fs.bpt;
+        beta_item_vec<64, Fin, true>(T, F, N, (int32_t)(idx / fs.bpt), bt, betaR, betaL,
+                                     (double2*)smem);
+        fuse_signal(beta_done + tau * kSyncStride);
+    }
+}
+
+__global__ void k_zero_i32(int* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ==========================================================================
 // batch kernels: one 1-D launch per step over the work items of all
 // matrices; item ranges per matrix are prefix sums in the descriptors, and
 // own[item] names the matrix of each item (one scalar load in place of a
@@ -1039,7 +1312,7 @@ __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict_
 __global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
     const BatchDesc* __restrict__ D, const int32_t* __restrict__ own) {
     // carries 2 G R + factors 2 G + S^R by row G per R, with G R <= 256
-    __shared__ double S[2 * kScanBatchThreads + 2 * kScanBatchMaxGroups +
+    __shared__ double S[2 * kScanBatchThreads + 2 * kScanMaxGroupsSingle +
                         kScanBatchThreads * kScanMaxPerBatch];
     const int64_t item = xcd_item();
     const int32_t k = cst(own)[item];
@@ -1149,20 +1422,15 @@ hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, d
 }
 
 void batch_scan_shape(int32_t P, int32_t* per, int32_t* G, int32_t* lgR) {
-    // the fewest groups, a power of two Gp <= kScanBatchMaxGroups, whose
-    // blocks per group stay on the one-pass path (<= kScanMaxPerBatch); the
-    // workgroup then takes R = kScanBatchThreads / Gp right-hand sides, so
-    // small systems get many right-hand sides per workgroup and large ones
-    // many groups.  Past 32 x 16 interface rows the groups grow longer.
-    const int32_t nsep = P > 1 ? P - 1 : 1;
-    const int32_t need = (nsep + kScanMaxPerBatch - 1) / kScanMaxPerBatch;
-    int32_t gp = 1;
-    while (gp < need && gp < kScanBatchMaxGroups) gp *= 2;
-    const int32_t p = std::max<int32_t>(4, (nsep + gp - 1) / gp);
-    *per = p;
-    *G = (nsep + p - 1) / p;                 // <= gp
+    // the groups of the single-matrix scan (scan_shape: at least 4 blocks
+    // per group, at most kScanMaxGroupsSingle groups), so that a matrix's
+    // interface values are bitwise those of its single plan, on a workgroup
+    // of kScanBatchThreads: G groups x R = 2^lgR right-hand sides, R the
+    // largest power of two with G R <= kScanBatchThreads.  Small systems get
+    // many right-hand sides per workgroup, large ones many short groups.
+    scan_shape(P, kScanMaxGroupsSingle, per, G);
     int32_t lg = 0;
-    while ((1 << (lg + 1)) * gp <= kScanBatchThreads) ++lg;
+    while ((1 << (lg + 1)) * *G <= kScanBatchThreads) ++lg;
     *lgR = lg;
 }
 
@@ -1271,6 +1539,109 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N, i
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+bool fused_fits(const DevTables& t, const DevTables* halves, const void* F, int64_t N, int mode,
+                int order) {
+    if (mode == TDS_F32 || order == TDS_IFACE_DICHOTOMY || t.P < 2 || N == 0) return false;
+    if (!halves || halves->P != 2 * t.P || t.wpad_rows != 64) return false;
+    if (t.max_rows <= kHalfRows || t.max_rows > 2 * kHalfRows) return false;
+    const int V = mode == TDS_F64 ? 2 : 4;
+    return N % V == 0 && ((uintptr_t)F & 15) == 0;
+}
+
+int64_t fused_sync_ints(int64_t N) {
+    // tiles of at least kFuseCols columns: room for any tile width
+    return kSyncStride * (2 + 2 * ((N + kFuseCols - 1) / kFuseCols));
+}
+
+template <typename Fin, int KIND, bool DENSE, bool GEN>
+static hipError_t fused_t(const DevTables& t, const DevTables& h, const void* F, void* X,
+                          int64_t N, int passes, double* betaR, double* betaL, double* xsep,
+                          const double* Kt, int32_t Pc, int32_t Mr, int32_t lag, int32_t W,
+                          int* sync, hipStream_t s, const KTime* tm) {
+    constexpr int32_t V = std::is_same<Fin, float>::value ? 4 : 2;
+    FuseShape fs;
+    fs.W = W;
+    fs.T = (N + W - 1) / W;
+    // the interface items of a tile `lag` stages after its beta items, its
+    // sweeps `lag` stages later still: long enough that the items waited on
+    // have left the resident window (measured: an interface lag of 1 stage
+    // made the kernel 1.5x slower than 5-8 stages)
+    fs.LI = lag;
+    fs.LS = 2 * lag;
+    fs.bpt = (int32_t)(W / (V * kBetaRhs));
+    fs.spt = (int32_t)(W / kHalfRhs);
+    fs.nb = t.P * fs.bpt;
+    fs.ns = t.P * fs.spt;
+    int32_t per = 0, G = 0, lgR = 0;
+    if (DENSE) {
+        fs.rowtiles = (t.P - 1 + kDenseRows - 1) / kDenseRows;
+        fs.ni = (int32_t)(W / kDenseCols) * fs.rowtiles;
+    } else {
+        // the groups of k_iface (scan_shape), on 256 threads: G groups x
+        // 2^lgR right-hand sides; the same carries, bitwise the same values
+        scan_shape(t.P, kScanMaxGroupsSingle, &per, &G);
+        while ((1 << (lgR + 1)) * G <= kScanBatchThreads) ++lgR;
+        fs.rowtiles = 1;
+        fs.ni = (int32_t)(W >> lgR);
+    }
+    const int64_t items = fs.T * (int64_t)(fs.nb + fs.ni + fs.ns);
+    if (items > INT32_MAX) return hipErrorInvalidValue;
+    const int64_t nsync = kSyncStride * (2 + 2 * fs.T);
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nsync + kWG - 1) / kWG)), dim3(kWG), 0, s,
+                       sync, nsync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_k(k_fused<Fin, KIND, DENSE, GEN>, dim3((unsigned)items), dim3(2 * kHalfRhs), 0, s, tm,
+             t, h, (const Fin*)F, (double*)X, N, betaR, betaL, xsep, Kt, Pc, Mr, per, G, lgR,
+             passes, fs, sync);
+    return hipGetLastError();
+}
+
+template <typename Fin, int KIND, bool DENSE>
+static hipError_t fused_g(const DevTables& t, const DevTables& h, const void* F, void* X,
+                          int64_t N, int passes, double* betaR, double* betaL, double* xsep,
+                          const double* Kt, int32_t Pc, int32_t Mr, int32_t lag, int32_t W,
+                          int* sync, hipStream_t s, const KTime* tm) {
+    if (t.general)
+        return fused_t<Fin, KIND, DENSE, true>(t, h, F, X, N, passes, betaR, betaL, xsep, Kt, Pc,
+                                               Mr, lag, W, sync, s, tm);
+    return fused_t<Fin, KIND, DENSE, false>(t, h, F, X, N, passes, betaR, betaL, xsep, Kt, Pc,
+                                            Mr, lag, W, sync, s, tm);
+}
+
+template <bool DENSE>
+static hipError_t fused_m(const DevTables& t, const DevTables& h, const void* F, void* X,
+                          int64_t N, int mode, int passes, double* betaR, double* betaL,
+                          double* xsep, const double* Kt, int32_t Pc, int32_t Mr, int32_t lag,
+                          int32_t W, int* sync, hipStream_t s, const KTime* tm) {
+    switch (mode) {
+        case TDS_F64:
+            return fused_g<double, kSweep64, DENSE>(t, h, F, X, N, passes, betaR, betaL, xsep, Kt,
+                                                    Pc, Mr, lag, W, sync, s, tm);
+        case TDS_F32_WIDE:
+            return fused_g<float, kSweep64, DENSE>(t, h, F, X, N, passes, betaR, betaL, xsep, Kt,
+                                                   Pc, Mr, lag, W, sync, s, tm);
+        case TDS_F32_REFINED:
+            return fused_g<float, kSweepRefined, DENSE>(t, h, F, X, N, passes, betaR, betaL,
+                                                        xsep, Kt, Pc, Mr, lag, W, sync, s, tm);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fused(const DevTables& t, const DevTables& h, const void* F, void* X,
+                        int64_t N, int mode, int passes, double* betaR, double* betaL,
+                        double* xsep, const double* Kt, int32_t Pc, int32_t Mr, int32_t lag,
+                        int32_t W, int* sync, hipStream_t s, const KTime* tm) {
+    if (lag < 1 || !sync || W < kFuseCols || W % kFuseCols != 0) return hipErrorInvalidValue;
+    if (Kt && (Pc % 4 != 0 || Pc < t.P || Mr % kDenseRows != 0 || Mr < t.P - 1))
+        return hipErrorInvalidValue;
+    if (Kt)
+        return fused_m<true>(t, h, F, X, N, mode, passes, betaR, betaL, xsep, Kt, Pc, Mr, lag, W,
+                             sync, s, tm);
+    return fused_m<false>(t, h, F, X, N, mode, passes, betaR, betaL, xsep, Kt, Pc, Mr, lag, W,
+                          sync, s, tm);
 }
 
 template <int TM>

@@ -79,11 +79,22 @@ class FourierPoisson2D:
         self.plan = t.BatchPlan(self._a, self._b, Ps)
 
     def solve(self, f, stream=None):
-        """u for the S right-hand sides f, shape (S, N1-1, N2-1)."""
+        """u for the S right-hand sides f, shape (S, N1-1, N2-1).  With
+        `stream` (a torch.cuda.Stream), every step (the transforms, the
+        copies and the batch solve) runs on it, in order."""
+        import contextlib
+
         import torch
         S, M, L = self.S, self.N1 - 1, self.N2 - 1
         if tuple(f.shape) != (S, M, L):
             raise ValueError(f"f must have shape {(S, M, L)}")
+        ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+        with ctx:
+            return self._solve(f, None)
+
+    def _solve(self, f, stream):
+        import torch
+        S, M, L = self.S, self.N1 - 1, self.N2 - 1
         wdt = torch.float64 if self.mode == "f64" else torch.float32
         # harmonics of f along y, scaled to the right-hand side h1^2 f~(l) and
         # written straight into the RHS-interleaved layout (l, i, S) by one

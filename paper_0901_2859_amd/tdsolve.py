@@ -34,7 +34,7 @@ SYMBOLS = [
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
     "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
-    "tdsolve_status", "tdsolve_strided_copy",
+    "tdsolve_status", "tdsolve_strided_copy", "tdsolve_set_fused",
 ]
 
 _lib = None
@@ -71,6 +71,7 @@ def lib():
     L.tdsolve_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp]
     L.tdsolve_residual.argtypes = [vp, vp, vp, i64, i32, vp, vp]
     L.tdsolve_set_refinement.argtypes = [vp, i32]
+    L.tdsolve_set_fused.argtypes = [vp, i32, i32]
     L.tdsolve_set_interface.argtypes = [vp, i32]
     L.tdsolve_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.tdsolve_prepare_host.argtypes = [dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
@@ -268,6 +269,12 @@ class Plan:
 
     def set_refinement(self, passes: int):
         _check(lib().tdsolve_set_refinement(self._h, int(passes)), "tdsolve_set_refinement")
+
+    def set_fused(self, lag: int, tile: int = 1024):
+        """The fused order (one launch; the sweeps of a tile of `tile`
+        right-hand sides `lag` tiles behind its weights), or the three
+        launches (lag 0)."""
+        _check(lib().tdsolve_set_fused(self._h, int(lag), int(tile)), "tdsolve_set_fused")
 
     def _check_tensor(self, t, dtype: str, name: str, rows: Optional[int] = None):
         import torch

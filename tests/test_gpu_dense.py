@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
 from oracle import method  # noqa: E402
+from tests import _parity  # noqa: E402
 from paper_0901_2859_amd import tdsolve as t  # noqa: E402
 from paper_0901_2859_amd import workloads as wl  # noqa: E402
 
@@ -27,10 +28,7 @@ DEV = "cuda:0"
 
 
 def _tol(a, b, F, ref, P):
-    tt, s = method.partition(len(b), P)
-    G = method.green_rows(a, b, s[1:P])
-    cond = (np.abs(G).T @ np.abs(F)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
-    return 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+    return _parity.tol64(a, b, F, ref, P)
 
 
 @pytest.mark.parametrize("M,N,P", [(64, 16, 16), (300, 77, 10), (1024, 300, 64), (130, 5, 65),
@@ -69,8 +67,8 @@ def test_dense_full_solve_poisson_all_modes():
     Fs = torch.from_numpy(F32).to(DEV)
     for mode, Fin in (("f64", Fs.double()), ("f32_refined", Fs), ("f32_wide", Fs)):
         X = plan.solve(Fin, mode=mode).cpu().numpy()
-        e = np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)
-        assert np.all(e <= tol), (mode, e.max())
+        _parity.check(X, ref, tol, f"dense poisson 4096x1000 {mode}")
+        _parity.check_residual(a, b, Fw, X, ref, f"dense poisson 4096x1000 {mode}")
 
 
 def test_dense_general_matrix_matches_oracle():
@@ -89,9 +87,9 @@ def test_dense_general_matrix_matches_oracle():
     X_r = plan.solve(Fd, mode="f64").cpu().numpy()
     plan.set_interface("dense")
     X_d = plan.solve(Fd, mode="f64").cpu().numpy()
-    scale = np.max(np.abs(ref), axis=0)
-    assert np.max(np.abs(X_d - ref).max(axis=0) / scale) <= 1e-11
-    assert np.max(np.abs(X_d - X_r).max(axis=0) / scale) <= 1e-11
+    tol = _parity.tol64(up, d, F, ref, P, lower=lo)
+    _parity.check(X_d, ref, tol, "dense general f64")
+    _parity.check(X_r, ref, tol, "recurrence general f64")
 
 
 def test_dense_limits_and_single_block():

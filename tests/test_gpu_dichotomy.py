@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
 from oracle import method  # noqa: E402
+from tests import _parity  # noqa: E402
 from paper_0901_2859_amd import tdsolve as t  # noqa: E402
 from paper_0901_2859_amd import workloads as wl  # noqa: E402
 
@@ -22,10 +23,7 @@ DEV = "cuda:0"
 
 
 def _tol(a, b, F, ref, P):
-    tt, s = method.partition(len(b), P)
-    G = method.green_rows(a, b, s[1:P])
-    cond = (np.abs(G).T @ np.abs(F)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
-    return 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+    return _parity.tol64(a, b, F, ref, P)
 
 
 @pytest.mark.parametrize("M,N,P", [(64, 16, 16), (300, 77, 10), (1024, 300, 64), (130, 5, 65),
@@ -69,8 +67,8 @@ def test_dichotomy_full_solve_poisson_all_modes():
     Fs = torch.from_numpy(F32).to(DEV)
     for mode, Fin in (("f64", Fs.double()), ("f32_refined", Fs), ("f32_wide", Fs)):
         X = plan.solve(Fin, mode=mode).cpu().numpy()
-        e = np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)
-        assert np.all(e <= tol), (mode, e.max())
+        _parity.check(X, ref, tol, f"dichotomy poisson 1024x512 {mode}")
+        _parity.check_residual(a, b, Fw, X, ref, f"dichotomy poisson 1024x512 {mode}")
 
 
 def test_set_interface_rejects_unknown_order():

@@ -65,3 +65,21 @@ def test_fourier_eigenfunctions_and_manufactured(tmp_path, monkeypatch):
         u = fq.solve(torch.from_numpy((8 * np.pi ** 2 * ue)[None]).to(DEV)).cpu().numpy()[0]
         errs.append(np.max(np.abs(u - ue)))
     assert 3.8 < errs[0] / errs[1] < 4.2, errs
+
+
+def test_fourier_on_a_side_stream(tmp_path, monkeypatch):
+    # with a stream argument every step (transforms, copies, batch solve)
+    # runs on that stream: the result equals the default-stream solve
+    monkeypatch.setenv("TDSOLVE_AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
+    rng = np.random.default_rng(77)
+    N1, N2, S = 96, 80, 40
+    f = torch.from_numpy(rng.uniform(-1, 1, size=(S, N1 - 1, N2 - 1))).to(DEV)
+    fp = FourierPoisson2D(N1, N2, S, mode="f64")
+    ref = fp.solve(f)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        u = fp.solve(f, stream=side)
+        side.synchronize()
+        assert torch.equal(u, ref), rep

@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
 from oracle import method  # noqa: E402
+from tests import _parity  # noqa: E402
 from paper_0901_2859_amd import tdsolve as t  # noqa: E402
 
 DEV = "cuda:0"
@@ -41,21 +42,13 @@ def _oracle(lo, d, up, F):
 
 
 def _tol(lo, d, up, F, ref, P):
-    M = len(d)
-    if P < 2:
-        return np.full(F.shape[1], 1e-11)
-    tt, s = method.partition(M, P)
-    Ainv = np.linalg.inv(np.diag(d) + np.diag(lo, -1) + np.diag(up, 1))
-    G = Ainv[s[1:P], :]
-    cond = (np.abs(G) @ np.abs(F)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
-    return 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+    # rows of the non-symmetric A^{-1} in the interface condition number,
+    # the comparison matrix of the non-symmetric A in the componentwise one
+    return _parity.tol64(up, d, F, ref, P, lower=lo)
 
 
 def _check(X, ref, tol, what):
-    e = np.max(np.abs(np.asarray(X, np.float64) - ref), axis=0) / np.maximum(
-        np.max(np.abs(ref), axis=0), 1e-300)
-    bad = np.nonzero(e > tol)[0]
-    assert bad.size == 0, f"{what}: columns {bad[:5]} e={e[bad[:5]]} tol={tol[bad[:5]]}"
+    _parity.check(X, ref, tol, what)
 
 
 @pytest.mark.parametrize("M,N,P,gamma", [

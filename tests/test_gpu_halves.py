@@ -8,9 +8,10 @@ row: blocks of 35 rows), one block (no interface rows), column counts that
 leave part of the last workgroup idle, a non-symmetric matrix, and the
 partition just below the split (blocks of 34 rows, swept whole).
 
-Tolerances as in the parity tests: per right-hand side
-1e-11 + 8 (t + 2P) u cond_n relative to the largest solution component,
-and the relative residual within 1e-10 of the oracle's."""
+Gates as in the parity tests (tests/_parity.py): per right-hand side the
+forward error within C u (cs_n + co_n + t) of the oracle's solution, and
+the relative residual, computed on the host by the oracle's routine, within
+1e-10 of the oracle's."""
 import numpy as np
 import pytest
 
@@ -19,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
 from oracle import method  # noqa: E402
+from tests import _parity  # noqa: E402
 from paper_0901_2859_amd import tdsolve as t  # noqa: E402
 from paper_0901_2859_amd import workloads as wl  # noqa: E402
 
@@ -26,19 +28,11 @@ DEV = "cuda:0"
 
 
 def _tol(a, b, F, ref, P):
-    if P < 2:
-        return np.full(F.shape[1], 1e-11)
-    tt, s = method.partition(len(b), P)
-    G = method.green_rows(a, b, s[1:P])
-    cond = (np.abs(G).T @ np.abs(F)).max(axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
-    return 1e-11 + 8 * (tt.max() + 2 * P) * 2.0 ** -53 * cond
+    return _parity.tol64(a, b, F, ref, P)
 
 
 def _r2(a, b, F, X):
-    R = F - b[:, None] * X
-    R[:-1] -= a[:, None] * X[1:]
-    R[1:] -= a[:, None] * X[:-1]
-    return np.linalg.norm(R, axis=0) / np.maximum(np.linalg.norm(F, axis=0), 1e-300)
+    return method.residual_columns(a, b, F, X)["r2"]
 
 
 @pytest.mark.parametrize("M,N,P,halves", [
@@ -64,11 +58,9 @@ def test_halves_match_oracle(M, N, P, halves, mode):
     assert plan.P == P and plan.info().sweep_halves == halves
     Fd = torch.from_numpy(F32).to(DEV)
     X = plan.solve(Fd.double() if mode == "f64" else Fd, mode=mode).cpu().numpy()
-    e = np.max(np.abs(X - ref), axis=0) / np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
-    tol = _tol(a, b, F, ref, P)
-    bad = np.nonzero(e > tol)[0]
-    assert bad.size == 0, (bad[:5], e[bad[:5]], tol[bad[:5]])
-    assert np.all(_r2(a, b, F, X) <= _r2(a, b, F, ref) + 1e-10)
+    what = f"halves M={M} N={N} P={P} {mode}"
+    _parity.check(X, ref, _tol(a, b, F, ref, P), what)
+    _parity.check_residual(a, b, F, X, ref, what)
 
 
 def test_refined_halves_poisson_passes():
@@ -106,8 +98,7 @@ def test_refined_halves_general_matrix():
     plan = t.Plan.general(lo, d, up, P)
     assert plan.info().sweep_halves == 1
     X = plan.solve(torch.from_numpy(F32).to(DEV), mode="f32_refined").cpu().numpy()
-    scale = np.max(np.abs(ref), axis=0)
-    assert np.max(np.abs(X - ref).max(axis=0) / scale) <= 1e-11
+    _parity.check(X, ref, _parity.tol64(up, d, F, ref, P, lower=lo), "halves general refined")
 
 
 def test_refined_halves_reproducible_and_in_place_of_rows():
