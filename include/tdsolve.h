@@ -71,7 +71,9 @@ typedef enum {
     TDS_ENOMEM = -3,        /* host or device allocation failed */
     TDS_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
     TDS_ENOCONV = -5,       /* reserved: refinement did not converge */
-    TDS_EUNSUPPORTED = -6   /* valid request outside what the library handles */
+    TDS_EUNSUPPORTED = -6,  /* valid request outside what the library handles */
+    TDS_ESCRATCH = -7       /* tdsolve_series_noalloc: the call's work area exceeds
+                               the library's fixed 32 MiB scratch */
 } tds_status;
 
 typedef enum {
@@ -134,6 +136,26 @@ int tdsolve_prepare_general(const double* lower, const double* diag,
  * `stream`. */
 int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N,
                    int32_t mode, void* stream);
+
+/* tdsolve_series without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, checks, kernels and results
+ * (bitwise) as tdsolve_series on the same plan, but the per-right-hand-side
+ * work area (beta^R, beta^L: P x N doubles each; the interface values:
+ * (P-1) x N doubles; with TDS_IFACE_DICHOTOMY two more (P+1) x N; the
+ * counters of the fused order, 2 + 2 ceil(N / 256) lines of 256 bytes;
+ * every slice rounded up to 256 bytes) comes from a fixed 32 MiB device
+ * array of the library instead of the plan's work buffer: N <= 10943 at
+ * P = 128, N <= 21930 at P = 64 (the recurrence and dense orders).  A larger request returns TDS_ESCRATCH
+ * before anything is launched.  The call allocates nothing (no hipMalloc,
+ * no hipFree, no host allocation); the array's address on the current
+ * device is looked up once, on the first call on that device.  The plan
+ * must have been prepared on the current device (else TDS_EINVAL).  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (concurrent streams, threads) race and must not be issued.  The
+ * call is not recorded for tdsolve_status and takes no phase timing. */
+int tdsolve_series_noalloc(tds_handle h, const void* F, void* X, int64_t N,
+                           int32_t mode, void* stream);
 
 /* Algorithm 3 alone: the solution components at the P-1 interface rows for
  * every right-hand side, without the block sweeps.  Xsep: device double
@@ -210,8 +232,8 @@ int tdsolve_timing_read(tds_handle h, double* ms, int64_t* calls);
 enum { TDS_IFACE_RECURRENCE = 0, TDS_IFACE_DICHOTOMY = 1, TDS_IFACE_DENSE = 2 };
 int tdsolve_set_interface(tds_handle h, int32_t order);
 
-/* Fused order of the per-right-hand-side step for tdsolve_series of a
- * single-matrix plan.  lag == 0 (default): three
+/* Fused order of the per-right-hand-side step for tdsolve_series and
+ * tdsolve_series_noalloc of a single-matrix plan.  lag == 0 (default): three
  * launches over the whole series (beta weights, interface values, block
  * sweeps).  lag >= 1: one launch (after a small one that clears its
  * counters) whose workgroups take the work items in ticket order, tile by

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -405,6 +406,35 @@ void remember(tds_plan* h, const void* const* F, void* const* X, const int64_t* 
     h->have_last = true;
 }
 
+// ---- fixed work area of tdsolve_series_noalloc ----------------------------
+// The beta weights and interface values of that entry point live in this
+// file-scope device array instead of the plan's growing work buffer.  Each
+// GPU that loads the library holds its own copy for the life of the
+// process.  Host code never passes the array's name to a kernel or a copy:
+// its device address is taken once per device with hipGetSymbolAddress and
+// kept in noalloc_base[].
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+void* noalloc_base[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first
+// call per device); TDS_OK or TDS_EHIP
+int noalloc_scratch(int device, char** out) {
+    if (device < 0 || device >= kMaxDevices) return TDS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_base[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return TDS_EHIP;
+        noalloc_base[device] = ptr;
+    }
+    *out = (char*)noalloc_base[device];
+    return TDS_OK;
+}
+
 constexpr int32_t kFuseMaxLag = 64;
 
 }  // namespace
@@ -456,6 +486,27 @@ int tdsolve_series(tds_handle h, const void* F, void* X, int64_t N, int32_t mode
         remember(h, &F, &Xv, &N, 1, mode);
     }
     return rc;
+}
+
+int tdsolve_series_noalloc(tds_handle h, const void* F, void* X, int64_t N, int32_t mode,
+                           void* stream) {
+    int rc = check_common(h, N, mode);
+    if (rc) return rc;
+    if (N == 0) return TDS_OK;
+    if (!F || !X) return TDS_EINVAL;
+    if (F == X && f_elem(mode) != x_elem(mode)) return TDS_EINVAL;
+    const size_t cells = (size_t)h->dev.M * (size_t)N;
+    if (overlap(F, cells * f_elem(mode), X, cells * x_elem(mode))) return TDS_EINVAL;
+    if (work_bytes(h, N, nullptr, nullptr, nullptr) > kNoAllocScratchBytes) return TDS_ESCRATCH;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return TDS_EHIP;
+    if (device != h->device) return TDS_EINVAL;
+    char* base = nullptr;
+    rc = noalloc_scratch(device, &base);
+    if (rc) return rc;
+    Work w;
+    carve_work(h, N, base, w);
+    return series_impl(h, F, X, N, mode, (hipStream_t)stream, mode, &w);
 }
 
 int tdsolve_components(tds_handle h, const void* F, double* Xsep, int64_t N, int32_t mode,
@@ -692,6 +743,8 @@ const char* tdsolve_strerror(int code) {
         case TDS_EHIP: return "HIP runtime or launch failure";
         case TDS_ENOCONV: return "refinement did not converge";
         case TDS_EUNSUPPORTED: return "unsupported size or mode";
+        case TDS_ESCRATCH:
+            return "work area larger than the 32 MiB fixed scratch of tdsolve_series_noalloc";
         default: return "unknown tdsolve status";
     }
 }

@@ -34,7 +34,7 @@ SYMBOLS = [
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
     "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
-    "tdsolve_status", "tdsolve_strided_copy", "tdsolve_set_fused",
+    "tdsolve_status", "tdsolve_strided_copy", "tdsolve_series_noalloc", "tdsolve_set_fused",
 ]
 
 _lib = None
@@ -67,6 +67,7 @@ def lib():
     L.tdsolve_prepare.argtypes = [dp, dp, i64, i32, ctypes.POINTER(vp)]
     L.tdsolve_prepare_general.argtypes = [dp, dp, dp, i64, i32, ctypes.POINTER(vp)]
     L.tdsolve_series.argtypes = [vp, vp, vp, i64, i32, vp]
+    L.tdsolve_series_noalloc.argtypes = [vp, vp, vp, i64, i32, vp]
     L.tdsolve_components.argtypes = [vp, vp, vp, i64, i32, vp]
     L.tdsolve_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp]
     L.tdsolve_residual.argtypes = [vp, vp, vp, i64, i32, vp, vp]
@@ -301,6 +302,21 @@ class Plan:
         _check(lib().tdsolve_series(self._h, ctypes.c_void_p(F.data_ptr()),
                                     ctypes.c_void_p(X.data_ptr()), N, m, _stream_ptr(stream)),
                "tdsolve_series")
+        return X
+
+    def solve_noalloc(self, F, X, mode=None, stream=None):
+        """As solve() into a given X, by the entry point that allocates
+        nothing (tdsolve_series_noalloc: the work area is the library's fixed
+        device scratch, shared by every call on the GPU)."""
+        import torch
+        m = mode_id(mode if mode is not None else ("f64" if F.dtype == torch.float64 else "f32_refined"))
+        self._check_tensor(F, _F_DTYPE[m], "F")
+        self._check_tensor(X, _X_DTYPE[m], "X")
+        if X.shape[1] != F.shape[1]:
+            raise ValueError("X and F differ in N")
+        _check(lib().tdsolve_series_noalloc(self._h, ctypes.c_void_p(F.data_ptr()),
+                                            ctypes.c_void_p(X.data_ptr()), F.shape[1], m,
+                                            _stream_ptr(stream)), "tdsolve_series_noalloc")
         return X
 
     def components(self, F, mode=None, stream=None):

@@ -8,10 +8,13 @@ solution is also held to the oracle's gates (tests/_parity.py).
 
 Shapes: several tiles with a ragged last one, a lag longer than the series,
 N not a multiple of the 256-RHS tile, both interface orders, every mode
-with FP64 results, a non-symmetric matrix, and replays of a captured graph.  Shapes outside the fused order
+with FP64 results, a non-symmetric matrix, the entry point that allocates
+nothing, and replays of a captured graph.  Shapes outside the fused order
 (N % 4 != 0, unaligned F, the dichotomy order, the FP32-result mode) must
 fall back to the three launches with the same result.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -129,7 +132,7 @@ def test_fused_falls_back_outside_its_shapes(case):
     assert torch.equal(X0, X1)
 
 
-def test_fused_graph_replays():
+def test_fused_noalloc_and_graph_replays():
     rng = np.random.default_rng(11)
     M, N, P = 4096, 2048, 64
     a, b = _dominant(rng, M)
@@ -140,6 +143,12 @@ def test_fused_graph_replays():
     ref = plan.solve(F, mode="f32_refined")
     plan.set_fused(2)
     X = torch.full_like(ref, float("nan"))
+    rc = t.lib().tdsolve_series_noalloc(plan._h, ctypes.c_void_p(F.data_ptr()),
+                                        ctypes.c_void_p(X.data_ptr()), N, t.MODES["f32_refined"],
+                                        t._stream_ptr(None))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref)
     s = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
