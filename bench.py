@@ -58,19 +58,24 @@ def parse():
     p.add_argument("--N", type=int, default=0)
     p.add_argument("--P", type=int, default=0)
     p.add_argument("--passes", type=int, default=None,
-                   help="refinement passes of the f32_refined mode; default: the fewest that "
-                        "reach the residual of more passes on the workload (measured): 1 for "
-                        "the Poisson series, 2 (the library default) for the others")
+                   help="refinement passes of the f32_refined mode; default: the autotuner's "
+                        "(the fewest whose residual on the workload's right-hand sides stays "
+                        "within twice that of the FP64-arithmetic solve)")
     p.add_argument("--interface", default="auto",
                    choices=["auto", "recurrence", "dichotomy", "dense"],
                    help="evaluation order of the interface values (single-matrix workloads); "
-                        "auto: dense (Theorem 2's double sum on the FP64 matrix cores) for "
-                        "P <= 64, recurrence above, the faster order measured on each side")
+                        "auto: the autotuner's measured choice")
     p.add_argument("--fused", type=int, default=None,
-                   help="lag of the fused order in tiles of 256 right-hand sides (single-matrix "
-                        "workloads; 0: three launches per solve)")
-    p.add_argument("--graph", action="store_true",
-                   help="time replays of a captured HIP graph per step instead of eager launches")
+                   help="lag of the fused order (single-matrix workloads; 0: three launches "
+                        "per solve); default: the autotuner's measured choice")
+    p.add_argument("--batch-rows", type=int, default=0, choices=[0, 32, 64],
+                   help="rows per block of the uneven batch (0: the batch autotuner's choice; "
+                        "32 or 64 fix it, e.g. to profile one configuration)")
+    p.add_argument("--launch", default="auto", choices=["auto", "eager", "graph"],
+                   help="time eager launches or replays of a captured HIP graph per step; auto: "
+                        "graph replays for the uneven batch, eager launches for the "
+                        "single-matrix workloads (replays measured slower there: Poisson "
+                        "56.1 against 51.0 us per step, ADI 231.6 against 227.5 us)")
     p.add_argument("--sets", type=int, default=0,
                    help="buffer sets rotated across steps (0: enough to exceed 512 MB)")
     p.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison runs")
@@ -131,6 +136,12 @@ def copy_bandwidth(torch, dev, mib=512, reps=20):
     del src, dst
     return {"kernel": "torch copy_", "bytes_per_launch": 2 * (mib << 20), "ms_per_launch": round(ms, 5),
             "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def graph_for(args, kind):
+    """Whether a workload of `kind` ('single' or 'batch') is timed from graph
+    replays."""
+    return args.launch == "graph" or (args.launch == "auto" and kind == "batch")
 
 
 def time_steps(solve, n_sets, steps, warmup, graph, timed_plan, torch):
@@ -209,16 +220,34 @@ class Single:
         self.plan = t.Plan(self.a, self.b, P)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
-        order = args.interface
-        if order == "auto":
-            order = "dense" if P <= 64 else "recurrence"
+        # interface order, fused order and refinement passes: measured by the
+        # autotuner on the workload's own right-hand sides (the block count
+        # is the workload's)
+        self.tuning = None
+        if args.interface == "auto" or args.fused is None or args.passes is None:
+            Fd = torch.from_numpy(self.F32).to("cuda:0")
+            if F_BYTES[args.mode] == 8:
+                Fd = Fd.double()
+            self.tuning = t.autotune_plan(self.a, self.b, N, args.mode, P=P, F=Fd)
+            del Fd
+        order = self.tuning["order"] if args.interface == "auto" else args.interface
         self.plan.set_interface(order)
-        self.plan.set_refinement(args.passes)
-        lag = args.fused if args.fused is not None else 0
-        self.plan.set_fused(lag)
+        if args.passes is not None:
+            self.passes = args.passes
+        elif args.mode == "f32_refined":
+            self.passes = self.tuning["passes"]
+        else:
+            self.passes = 2
+        self.plan.set_refinement(self.passes)
+        if args.fused is None:
+            lag, tile = self.tuning["fuse_lag"], self.tuning["fuse_tile"]
+        else:
+            lag, tile = args.fused, 512
+        self.plan.set_fused(lag, tile or 512)
         self.unknowns = M * N
         self.config = {"workload": self.name, "M": M, "N": N, "P": P, "interface": order,
-                       "fused_lag": lag}
+                       "fused_lag": lag, "fused_tile": tile if lag else 0,
+                       "tuning": self.tuning}
 
     def sweep_bytes(self, mode):
         # the block sweep reads F, writes X, reads two interface values per
@@ -240,11 +269,11 @@ class Single:
         def solve(k):
             self.plan.solve(Fs[k % n_sets], Xs[k % n_sets], mode=mode)
 
-        r = time_steps(solve, n_sets, steps, warmup, args.graph, self.plan, torch)
+        r = time_steps(solve, n_sets, steps, warmup, graph_for(args, "single"), self.plan, torch)
         if n_sets > 1:
             # warm: one buffer set, which the last-level cache may hold
             warm = time_steps(lambda k: self.plan.solve(Fs[0], Xs[0], mode=mode), 1,
-                              max(10, steps // 2), 3, args.graph, self.plan, torch)
+                              max(10, steps // 2), 3, graph_for(args, "single"), self.plan, torch)
             r["warm_ms_per_step"] = warm["ms_per_step"]
         eta, r2 = self.plan.residual(Fs[0], Xs[0], mode=mode)
         torch.cuda.synchronize()
@@ -286,17 +315,30 @@ class Batch:
         self.b = [it["b"] for it in self.items]
         self.Ms = [it["M"] for it in self.items]
         self.Ns = [it["N"] for it in self.items]
-        self.P, self.tune_ms = t.batch_autotune(self.a, self.b, self.Ns, args.mode)
+        self.P, tuned_passes, self.tune_ms = t.batch_autotune(self.a, self.b, self.Ns, args.mode,
+                                                              with_passes=True)
+        if args.batch_rows:
+            self.P = [1 if m < 4 else max(1, min(-(-m // args.batch_rows), m // 2, 65535))
+                      for m in self.Ms]
+        if args.passes is not None:
+            self.passes = args.passes
+        elif args.mode == "f32_refined":
+            self.passes = tuned_passes
+        else:
+            self.passes = 2
         t0 = time.perf_counter()
         self.plan = t.BatchPlan(self.a, self.b, self.P)
-        self.plan.set_refinement(args.passes)
+        self.plan.set_refinement(self.passes)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
         self.unknowns = sum(m * n for m, n in zip(self.Ms, self.Ns))
         self.name = ("uneven batch: 256 matrices, M log-uniform [128, 16384], b = 2 + U[0.01, 1], "
                      "a = -1, N uniform [1, 2048], FP32 storage")
         self.config = {"workload": self.name, "K": len(self.items), "unknowns": self.unknowns,
-                       "rows_per_block": max(-(-m // p) for m, p in zip(self.Ms, self.P))}
+                       "rows_per_block": max(-(-m // p) for m, p in zip(self.Ms, self.P)),
+                       "tuning": {"rows_per_block": max(-(-m // p) for m, p in
+                                                        zip(self.Ms, self.P)),
+                                  "passes": tuned_passes, "ms": self.tune_ms}}
 
     def sweep_bytes(self, mode):
         return sum(m * n * (F_BYTES[mode] + X_BYTES[mode]) + 2 * (p - 1) * n * 8
@@ -315,7 +357,7 @@ class Batch:
         def solve(k):
             self.plan.solve(Fs, Xs, mode=mode)
 
-        r = time_steps(solve, 1, steps, warmup, args.graph, self.plan, torch)
+        r = time_steps(solve, 1, steps, warmup, graph_for(args, "batch"), self.plan, torch)
         # residuals of every matrix of the batch: the largest normwise
         # backward error from the library (tdsolve_status, which recomputes
         # the last batch solve's residuals), and the relative 2-norm residual
@@ -364,7 +406,8 @@ class Gradient(Single):
         self.a, self.b, self.F32, self.W = w["a"], w["b"], w["F"], w["W"]
         t0 = time.perf_counter()
         self.plan = t.Plan(self.a, self.b, self.P)
-        self.plan.set_refinement(args.passes)
+        self.passes = args.passes if args.passes is not None else 2
+        self.plan.set_refinement(self.passes)
         torch.cuda.synchronize()
         self.prepare_ms = (time.perf_counter() - t0) * 1e3
         self.unknowns = self.M * self.N
@@ -386,7 +429,7 @@ class Gradient(Single):
             self.plan.solve(F, X, mode=mode)
             self.plan.backward(X, W, mode=mode)
 
-        r = time_steps(solve, 1, steps, warmup, self.args.graph, self.plan, torch)
+        r = time_steps(solve, 1, steps, warmup, graph_for(self.args, "single"), self.plan, torch)
         eta, r2 = self.plan.residual(F, X, mode=mode)
         torch.cuda.synchronize()
         r["eta_max"], r["r2_max"], r["sets"] = float(eta.max()), float(r2.max()), 1
@@ -416,7 +459,8 @@ class Fourier:
     def solver(self, mode):
         if mode not in self.solvers:
             self.solvers[mode] = self.cls(self.n, self.n, self.S, mode=mode)
-            self.solvers[mode].plan.set_refinement(self.args.passes)
+            self.passes = self.args.passes if self.args.passes is not None else 2
+            self.solvers[mode].plan.set_refinement(self.passes)
         return self.solvers[mode]
 
     def sweep_bytes(self, mode):
@@ -435,7 +479,7 @@ class Fourier:
         def solve(k):
             fp.solve(f)
 
-        r = time_steps(solve, 1, steps, warmup, self.args.graph, fp.plan, torch)
+        r = time_steps(solve, 1, steps, warmup, graph_for(self.args, "batch"), fp.plan, torch)
         r["eta_max"], r["r2_max"], r["sets"] = None, None, 1
         return r
 
@@ -478,8 +522,7 @@ def workload_report(name, args, t, wl, torch, dev, mode, steps, warmup, passes=N
     a2 = argparse.Namespace(**vars(args))
     a2.workload = name
     a2.mode = mode
-    a2.passes = passes if passes is not None else (args.passes if args.passes is not None else
-                                                   (1 if name == "poisson" else 2))
+    a2.passes = passes if passes is not None else args.passes
     W = {"batch": Batch, "gradient": Gradient, "fourier": Fourier}.get(name, Single)(
         a2, t, wl, torch)
 
@@ -498,12 +541,15 @@ def workload_report(name, args, t, wl, torch, dev, mode, steps, warmup, passes=N
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
     batched = name in ("batch", "fourier")
     if batched:
-        kname = "k_sweep_batch"
+        rows = max(-(-m // p) for m, p in zip(W.Ms, W.P)) if name == "batch" else 0
+        kname = "k_sweep_batch_halves" if rows == 64 and mode != "f32" else "k_sweep_batch"
+        shape = f"{name}_r{rows}" if name == "batch" else name
     elif mode != "f32" and W.plan.info().sweep_halves:
         kname = "k_sweep_halves"
+        shape = f"{name}_{W.M}x{W.N}_P{W.P}"
     else:
         kname = "k_sweep_reg"
-    shape = (name if batched else f"{name}_{W.M}x{W.N}_P{W.P}")
+        shape = f"{name}_{W.M}x{W.N}_P{W.P}"
     # HBM bytes per launch measured by rocprofv3 counters for this kernel,
     # mode and workload; null unless taken from the current kernel sources
     tr = profdigest.read_traffic(os.path.join(
@@ -520,7 +566,7 @@ def workload_report(name, args, t, wl, torch, dev, mode, steps, warmup, passes=N
                 compare[m] = run(m, max(10, steps // 2), max(3, warmup // 2))
     cpu = None if args.no_cpu else W.cpu_baseline(args.cpu_seconds)
     rep = {
-        "config": dict(W.config, mode=mode, refine_passes=a2.passes,
+        "config": dict(W.config, mode=mode, refine_passes=W.passes,
                        layout="RHS-interleaved [M][N]",
                        buffer_sets=main_r["sets"], launch=main_r["launch"]),
         "value": main_r["unknowns_per_s"],

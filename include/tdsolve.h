@@ -305,6 +305,37 @@ int tdsolve_autotune(const double* a, const double* b, int64_t M, int64_t N,
                      int32_t mode, int32_t reps, int32_t* P_out, double* ms_out,
                      void* stream);
 
+/* A measured configuration of a single-matrix plan (tdsolve_autotune_plan). */
+typedef struct {
+    int32_t P;          /* block count */
+    int32_t order;      /* TDS_IFACE_RECURRENCE or TDS_IFACE_DENSE */
+    int32_t passes;     /* refinement passes for TDS_F32_REFINED (else 0) */
+    int32_t fuse_lag;   /* tdsolve_set_fused lag (0: three launches) */
+    int32_t fuse_tile;  /* tdsolve_set_fused tile */
+    int32_t pad_;
+    double ms;          /* milliseconds per solve of the choice */
+    double r2;          /* largest relative residual ||F - A X||_2 / ||F||_2 of
+                           the choice on the timing right-hand sides */
+} tds_tuning;
+
+/* Measured plan configuration for series of N right-hand sides in `mode`:
+ * the block count (P == 0: blocks of at most 16, 32, 64 or 128 rows, and
+ * P = 1 for M <= 128; P > 0: that count), the interface order (recurrence,
+ * or the dense product for P <= 1024) and the fused order (three launches,
+ * or one launch with lag 8 over tiles of 512 right-hand sides, for plans
+ * that sweep in halves) are timed on F (device [M][N] of the mode's input
+ * type; NULL: device-generated uniform[-1, 1) values), each candidate in
+ * three interleaved rounds of `reps` calls (<= 0: 5), keeping its fastest
+ * round.  For TDS_F32_REFINED the refinement passes of each block count are
+ * fixed first, by accuracy: the fewest (1..3) whose largest relative
+ * residual on F is within twice that of the same plan's TDS_F32_WIDE solve
+ * (FP64 arithmetic).  Allocates and frees device memory and synchronises
+ * `stream`.  Errors: as tdsolve_prepare, TDS_EINVAL (N < 1, P < 0, bad mode,
+ * NULL out), TDS_ENOMEM, TDS_EHIP. */
+int tdsolve_autotune_plan(const double* a, const double* b, int64_t M, int64_t N,
+                          int32_t mode, int32_t P, const void* F, int32_t reps,
+                          tds_tuning* out, void* stream);
+
 int tdsolve_destroy(tds_handle h);
 
 const char* tdsolve_strerror(int code);
@@ -333,15 +364,21 @@ int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
 
 /* Measured block counts for a batch.  The batch kernels hold every block
  * in one common register row bucket, so the choice is the rows per block,
- * 32 or 64, shared by all matrices (P[k] = ceil(M[k] / rows) within the
- * method's limits); each choice is timed on tdsolve_batch_series with N[k]
- * device-generated right-hand sides, and the fastest P[k] are written to
- * P_out (K entries), the milliseconds per call to *ms_out (may be NULL).
- * Allocation, synchronisation and errors as tdsolve_autotune. */
+ * 32 or 64 (64: the sweeps take the blocks in halves), shared by all
+ * matrices (P[k] = ceil(M[k] / rows) within the method's limits); each
+ * choice is timed on tdsolve_batch_series with N[k] device-generated
+ * right-hand sides in three interleaved rounds, and the fastest P[k] are
+ * written to P_out (K entries), the milliseconds per call to *ms_out (may be
+ * NULL).  For TDS_F32_REFINED, *passes_out (may be NULL; 0 in other modes)
+ * receives the fewest refinement passes (1..3) whose largest normwise
+ * backward error (tdsolve_status) stays within twice that of the same batch
+ * solved in FP64 arithmetic (TDS_F32_WIDE).  Allocation, synchronisation and
+ * errors as tdsolve_autotune. */
 int tdsolve_batch_autotune(int32_t K, const double* const* a,
                            const double* const* b, const int64_t* M,
                            const int64_t* N, int32_t mode, int32_t reps,
-                           int32_t* P_out, double* ms_out, void* stream);
+                           int32_t* P_out, int32_t* passes_out, double* ms_out,
+                           void* stream);
 
 /* Scaled strided copy dst = alpha * src of an S x M x L array of doubles
  * (f64 != 0) or floats, for the drivers that move the series between a

@@ -1,5 +1,6 @@
 // Measured choice of the block decomposition (number of blocks P, hence
-// rows per block) for one matrix or for an uneven batch.
+// rows per block) for one matrix or for an uneven batch, and of the launch
+// configuration and refinement passes of a plan.
 //
 // The split into P blocks is a free parameter of the method (Algorithm 3
 // works for any P with blocks of at least 2 rows); it trades the
@@ -8,7 +9,10 @@
 // balance is fastest depends on M, N, the mode and the device, so the
 // candidates are simply timed: each one is prepared, solved on
 // uniform[-1, 1) right-hand sides of the caller's N (generated on the
-// device), and the fastest is returned.
+// device, or the caller's own), and the fastest is returned.  The number of
+// refinement passes is chosen by accuracy, not speed: the fewest passes
+// whose residual on the same right-hand sides stays within twice that of
+// the solve in FP64 arithmetic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,10 +72,34 @@ int time_calls(Run run, int32_t reps, hipStream_t s, Events& ev, double* ms) {
     return TDS_OK;
 }
 
+// Candidates are timed in interleaved rounds (every candidate once per
+// round) and each keeps its fastest round: a candidate timed first would
+// otherwise also pay for the device still raising its clocks.
+constexpr int kRounds = 3;
+// the fused order's candidate configuration (lag, tile)
+constexpr int32_t kTuneLag = 8;
+constexpr int32_t kTuneTile = 512;
+
 int alloc(DevBuf& b, size_t bytes) {
     const hipError_t e = hipMalloc(&b.p, std::max<size_t>(bytes, 256));
     if (e == hipErrorOutOfMemory) return TDS_ENOMEM;
     return e == hipSuccess ? TDS_OK : TDS_EHIP;
+}
+
+// largest relative 2-norm residual of the series in X (tdsolve_residual)
+int max_r2(tds_handle h, const void* F, const void* X, int64_t N, int32_t mode, double* out_dev,
+           hipStream_t s, double* r2) {
+    int rc = tdsolve_residual(h, F, X, N, mode, out_dev, s);
+    if (rc) return rc;
+    std::vector<double> host(2 * (size_t)N);
+    if (hipMemcpyAsync(host.data(), out_dev, sizeof(double) * host.size(), hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return TDS_EHIP;
+    double m = 0.0;
+    for (int64_t n = 0; n < N; ++n) m = std::max(m, host[N + n]);
+    *r2 = m;
+    return TDS_OK;
 }
 
 }  // namespace
@@ -98,30 +126,135 @@ int tdsolve_autotune(const double* a, const double* b, int64_t M, int64_t N, int
     Events ev;
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
         return TDS_EHIP;
-    double best = INFINITY;
-    int32_t bestP = 0;
-    for (int32_t P : cand) {
-        tds_handle h = nullptr;
-        rc = tdsolve_prepare(a, b, M, P, &h);
+    std::vector<tds_handle> hs(cand.size(), nullptr);
+    std::vector<double> best_ms(cand.size(), INFINITY);
+    for (size_t c = 0; c < cand.size() && !rc; ++c) rc = tdsolve_prepare(a, b, M, cand[c], &hs[c]);
+    for (int round = 0; round < kRounds && !rc; ++round)
+        for (size_t c = 0; c < cand.size() && !rc; ++c) {
+            double ms = 0.0;
+            rc = time_calls([&] { return tdsolve_series(hs[c], F.p, X.p, N, mode, stream); }, reps,
+                            s, ev, &ms);
+            best_ms[c] = std::min(best_ms[c], ms);
+        }
+    for (tds_handle h : hs)
+        if (h) tdsolve_destroy(h);
+    if (rc) return rc;
+    const size_t pick = std::min_element(best_ms.begin(), best_ms.end()) - best_ms.begin();
+    *P_out = cand[pick];
+    if (ms_out) *ms_out = best_ms[pick];
+    return TDS_OK;
+}
+
+int tdsolve_autotune_plan(const double* a, const double* b, int64_t M, int64_t N, int32_t mode,
+                          int32_t P, const void* Fin, int32_t reps, tds_tuning* out,
+                          void* stream) {
+    if (!out || M < 1 || N < 1 || P < 0 || mode < TDS_F64 || mode > TDS_F32_WIDE)
+        return TDS_EINVAL;
+    if (reps <= 0) reps = 5;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> cand;
+    if (P > 0) {
+        cand.push_back(P);
+    } else {
+        for (int32_t rows : {16, 32, 64, 128}) cand.push_back(blocks_for(M, rows));
+        if (M <= 128) cand.push_back(1);
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    }
+    DevBuf Fbuf, X, Xw, R;
+    int rc = TDS_OK;
+    const void* F = Fin;
+    if (!F) {
+        rc = alloc(Fbuf, f_bytes(mode) * (size_t)M * (size_t)N);
         if (rc) return rc;
-        double ms = 0.0;
-        rc = time_calls([&] { return tdsolve_series(h, F.p, X.p, N, mode, stream); }, reps, s,
-                        ev, &ms);
-        tdsolve_destroy(h);
-        if (rc) return rc;
-        if (ms < best) {
-            best = ms;
-            bestP = P;
+        if (launch_fill_uniform(Fbuf.p, M * N, mode != TDS_F64, 0x5eedull, s) != hipSuccess)
+            return TDS_EHIP;
+        F = Fbuf.p;
+    }
+    rc = alloc(X, x_bytes(mode) * (size_t)M * (size_t)N);
+    if (!rc && mode == TDS_F32_REFINED) rc = alloc(Xw, sizeof(double) * (size_t)M * (size_t)N);
+    if (!rc) rc = alloc(R, sizeof(double) * 2 * (size_t)N);
+    if (rc) return rc;
+    Events ev;
+    if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
+        return TDS_EHIP;
+
+    // one plan per block count; its refinement passes first (the fewest,
+    // 1..3, whose largest relative residual on these right-hand sides stays
+    // within twice that of the same solve in FP64 arithmetic), then the
+    // launch configurations timed under them
+    struct Cand {
+        size_t plan;
+        int32_t order, lag, tile;
+        double ms = INFINITY;
+    };
+    std::vector<tds_handle> hs(cand.size(), nullptr);
+    std::vector<int32_t> passes(cand.size(), 0);
+    std::vector<double> r2s(cand.size(), 0.0);
+    std::vector<Cand> cs;
+    for (size_t c = 0; c < cand.size() && !rc; ++c) {
+        rc = tdsolve_prepare(a, b, M, cand[c], &hs[c]);
+        if (rc) break;
+        tds_info info;
+        tdsolve_info(hs[c], &info);
+        if (mode == TDS_F32_REFINED) {
+            double r2w = 0.0;
+            rc = tdsolve_series(hs[c], F, Xw.p, N, TDS_F32_WIDE, stream);
+            if (!rc) rc = max_r2(hs[c], F, Xw.p, N, TDS_F32_WIDE, (double*)R.p, s, &r2w);
+            int32_t p = 1;
+            for (; !rc && p <= 3; ++p) {
+                double r2 = 0.0;
+                rc = tdsolve_set_refinement(hs[c], p);
+                if (!rc) rc = tdsolve_series(hs[c], F, X.p, N, mode, stream);
+                if (!rc) rc = max_r2(hs[c], F, X.p, N, mode, (double*)R.p, s, &r2);
+                r2s[c] = r2;
+                if (!rc && r2 <= 2.0 * r2w) break;
+            }
+            passes[c] = std::min<int32_t>(p, 3);
+            if (!rc) rc = tdsolve_set_refinement(hs[c], passes[c]);
+        }
+        const bool dense_ok = cand[c] >= 2 && cand[c] <= kDenseMaxBlocks;
+        for (int32_t order : {TDS_IFACE_RECURRENCE, TDS_IFACE_DENSE}) {
+            if (order == TDS_IFACE_DENSE && !dense_ok) continue;
+            cs.push_back({c, order, 0, 0});
+            if (info.sweep_halves && mode != TDS_F32) cs.push_back({c, order, kTuneLag, kTuneTile});
         }
     }
-    *P_out = bestP;
-    if (ms_out) *ms_out = best;
-    return TDS_OK;
+    for (int round = 0; round < kRounds && !rc; ++round)
+        for (Cand& k : cs) {
+            tds_handle h = hs[k.plan];
+            rc = tdsolve_set_interface(h, k.order);
+            if (!rc) rc = tdsolve_set_fused(h, k.lag, k.tile);
+            if (rc) break;
+            double ms = 0.0;
+            rc = time_calls([&] { return tdsolve_series(h, F, X.p, N, mode, stream); }, reps, s,
+                            ev, &ms);
+            k.ms = std::min(k.ms, ms);
+        }
+    if (!rc && !cs.empty()) {
+        const Cand& k = *std::min_element(cs.begin(), cs.end(),
+                                          [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+        out->P = cand[k.plan];
+        out->order = k.order;
+        out->passes = passes[k.plan];
+        out->fuse_lag = k.lag;
+        out->fuse_tile = k.tile;
+        out->ms = k.ms;
+        // the residual of the chosen configuration
+        tds_handle h = hs[k.plan];
+        rc = tdsolve_set_interface(h, k.order);
+        if (!rc) rc = tdsolve_set_fused(h, k.lag, k.tile);
+        if (!rc) rc = tdsolve_series(h, F, X.p, N, mode, stream);
+        if (!rc) rc = max_r2(h, F, X.p, N, mode, (double*)R.p, s, &out->r2);
+    }
+    for (tds_handle h : hs)
+        if (h) tdsolve_destroy(h);
+    return rc;
 }
 
 int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* const* b,
                            const int64_t* M, const int64_t* N, int32_t mode, int32_t reps,
-                           int32_t* P_out, double* ms_out, void* stream) {
+                           int32_t* P_out, int32_t* passes_out, double* ms_out, void* stream) {
     if (K < 1 || !a || !b || !M || !N || !P_out || mode < TDS_F64 || mode > TDS_F32_WIDE)
         return TDS_EINVAL;
     if (reps <= 0) reps = 5;
@@ -154,27 +287,46 @@ int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* cons
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
         return TDS_EHIP;
     // the batch kernels share one register row bucket: 32 or 64 rows
-    double best = INFINITY;
-    int32_t best_rows = 0;
+    const int32_t rows_c[2] = {32, 64};
+    tds_handle hs[2] = {nullptr, nullptr};
     std::vector<int32_t> P(K);
-    for (int32_t rows : {32, 64}) {
-        for (int32_t k = 0; k < K; ++k) P[k] = blocks_for(M[k], rows);
-        tds_handle h = nullptr;
-        rc = tdsolve_batch_prepare(K, a, b, M, P.data(), &h);
-        if (rc) return rc;
-        double ms = 0.0;
-        rc = time_calls(
-            [&] { return tdsolve_batch_series(h, Fp.data(), Xp.data(), N, mode, stream); }, reps,
-            s, ev, &ms);
-        tdsolve_destroy(h);
-        if (rc) return rc;
-        if (ms < best) {
-            best = ms;
-            best_rows = rows;
-        }
+    double best_ms[2] = {INFINITY, INFINITY};
+    for (int c = 0; c < 2 && !rc; ++c) {
+        for (int32_t k = 0; k < K; ++k) P[k] = blocks_for(M[k], rows_c[c]);
+        rc = tdsolve_batch_prepare(K, a, b, M, P.data(), &hs[c]);
     }
-    for (int32_t k = 0; k < K; ++k) P_out[k] = blocks_for(M[k], best_rows);
-    if (ms_out) *ms_out = best;
+    for (int round = 0; round < kRounds && !rc; ++round)
+        for (int c = 0; c < 2 && !rc; ++c) {
+            double ms = 0.0;
+            rc = time_calls(
+                [&] { return tdsolve_batch_series(hs[c], Fp.data(), Xp.data(), N, mode, stream); },
+                reps, s, ev, &ms);
+            best_ms[c] = std::min(best_ms[c], ms);
+        }
+    const int pick = best_ms[1] < best_ms[0] ? 1 : 0;
+    // refinement passes: the fewest (1..3) whose largest normwise backward
+    // error on these right-hand sides stays within twice that of the same
+    // solve in FP64 arithmetic (TDS_F32_WIDE)
+    int32_t passes = 0;
+    if (!rc && mode == TDS_F32_REFINED) {
+        double eta_wide = 0.0;
+        rc = tdsolve_batch_series(hs[pick], Fp.data(), Xp.data(), N, TDS_F32_WIDE, stream);
+        if (!rc) rc = tdsolve_status(hs[pick], stream, &eta_wide, nullptr);
+        for (passes = 1; !rc && passes <= 3; ++passes) {
+            double eta = 0.0;
+            rc = tdsolve_set_refinement(hs[pick], passes);
+            if (!rc) rc = tdsolve_batch_series(hs[pick], Fp.data(), Xp.data(), N, mode, stream);
+            if (!rc) rc = tdsolve_status(hs[pick], stream, &eta, nullptr);
+            if (!rc && eta <= 2.0 * eta_wide) break;
+        }
+        if (passes > 3) passes = 3;
+    }
+    for (int c = 0; c < 2; ++c)
+        if (hs[c]) tdsolve_destroy(hs[c]);
+    if (rc) return rc;
+    for (int32_t k = 0; k < K; ++k) P_out[k] = blocks_for(M[k], rows_c[pick]);
+    if (passes_out) *passes_out = passes;
+    if (ms_out) *ms_out = best_ms[pick];
     return TDS_OK;
 }
 

@@ -6,7 +6,8 @@
              `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs, each
              scaled by what the same counter reads for a plain streaming
              kernel of known size (a torch elementwise negation that reads and
-             writes the same number of bytes) in the same run.
+             writes the same number of bytes) in the same run;
+    path     the same for every kernel of one step of the path, and the sum.
 
 The traffic summary records a SHA-256 of the kernel sources and build flags;
 bench.py reports the figure only while that hash still matches the tree.
@@ -126,6 +127,41 @@ def cmd_traffic(a):
     _emit("\n".join(lines) + "\n", a.out)
 
 
+def cmd_path(a):
+    """HBM traffic of one step of the path: the per-dispatch traffic of each
+    kernel of the step (substrings in --kernels, each launched once per
+    step), scaled as in cmd_traffic, and their sum."""
+    fetch = counter_values(a.fetch, "FETCH_SIZE")
+    write = counter_values(a.write, "WRITE_SIZE")
+    cf, cw = _pick(fetch, a.copy_kernel), _pick(write, a.copy_kernel)
+    sf = a.copy_bytes / (statistics.median(fetch[cf]) * 1024.0)
+    sw = a.copy_bytes / (statistics.median(write[cw]) * 1024.0)
+    lines = [
+        "# HBM traffic of one step of the path from rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE),",
+        "# each kernel's median per dispatch scaled by the plain copy's counters",
+        f"# fetch command: {a.cmd_fetch}",
+        f"# write command: {a.cmd_write}",
+        f"source_sha256={source_hash()}",
+        f"fetch_scale={sf:.4f}",
+        f"write_scale={sw:.4f}",
+    ]
+    total_f = total_w = 0.0
+    for sub in a.kernels.split(";"):
+        kf, kw = _pick(fetch, sub), _pick(write, sub)
+        fb = statistics.median(fetch[kf]) * 1024.0 * sf
+        wb = statistics.median(write[kw]) * 1024.0 * sw
+        total_f += fb
+        total_w += wb
+        lines.append(f"kernel={kf} fetch_bytes={fb:.0f} write_bytes={wb:.0f}")
+    lines.append(f"path_fetch_bytes_per_step={total_f:.0f}")
+    lines.append(f"path_write_bytes_per_step={total_w:.0f}")
+    lines.append(f"path_traffic_bytes_per_step={total_f + total_w:.0f}")
+    if a.alg_bytes:
+        lines.append(f"algorithmic_bytes_per_step={a.alg_bytes}")
+        lines.append(f"traffic_over_algorithmic={(total_f + total_w) / a.alg_bytes:.4f}")
+    _emit("\n".join(lines) + "\n", a.out)
+
+
 def read_traffic(path: str):
     """(traffic bytes per launch, kernel) from a traffic summary, or None when
     the file is absent or was taken from other kernel sources."""
@@ -166,9 +202,21 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", default="")
     t.add_argument("--cmd-write", default="")
     t.add_argument("--out")
+    q = sub.add_parser("path")
+    q.add_argument("--fetch", required=True)
+    q.add_argument("--write", required=True)
+    q.add_argument("--kernels", required=True, help="kernel name substrings separated by semicolons")
+    q.add_argument("--copy-kernel", required=True)
+    q.add_argument("--copy-bytes", type=int, required=True)
+    q.add_argument("--alg-bytes", type=int, default=0)
+    q.add_argument("--cmd-fetch", default="")
+    q.add_argument("--cmd-write", default="")
+    q.add_argument("--out")
     a = p.parse_args(argv)
     if a.what == "stats":
         cmd_stats(a)
+    elif a.what == "path":
+        cmd_path(a)
     else:
         cmd_traffic(a)
 

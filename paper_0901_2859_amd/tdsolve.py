@@ -32,7 +32,7 @@ SYMBOLS = [
     "tdsolve_residual", "tdsolve_set_refinement", "tdsolve_info", "tdsolve_prepare_host",
     "tdsolve_default_blocks", "tdsolve_destroy", "tdsolve_strerror",
     "tdsolve_batch_prepare", "tdsolve_batch_series", "tdsolve_timing_enable",
-    "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune",
+    "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune", "tdsolve_autotune_plan",
     "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
     "tdsolve_status", "tdsolve_strided_copy", "tdsolve_series_noalloc", "tdsolve_set_fused",
 ]
@@ -45,6 +45,12 @@ class TdsError(RuntimeError):
         msg = _lib.tdsolve_strerror(code).decode() if _lib is not None else str(code)
         super().__init__(f"{where}: {msg} (status {code})")
         self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("order", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("fuse_lag", ctypes.c_int32), ("fuse_tile", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("ms", ctypes.c_double), ("r2", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -90,7 +96,9 @@ def lib():
     L.tdsolve_timing_enable.argtypes = [vp, i32]
     L.tdsolve_timing_read.argtypes = [vp, vp, vp]
     L.tdsolve_autotune.argtypes = [dp, dp, i64, i64, i32, i32, vp, vp, vp]
-    L.tdsolve_batch_autotune.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp, vp]
+    L.tdsolve_batch_autotune.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.tdsolve_autotune_plan.argtypes = [dp, dp, i64, i64, i32, i32, vp, i32,
+                                        ctypes.POINTER(Tuning), vp]
     for name in SYMBOLS:
         if name not in ("tdsolve_default_blocks", "tdsolve_strerror"):
             getattr(L, name).restype = ctypes.c_int
@@ -540,11 +548,13 @@ def autotune(a, b, N: int, mode="f32_refined", reps: int = 5, cache: bool = True
 
 
 def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
-                   cache: bool = True, stream=None):
+                   cache: bool = True, stream=None, with_passes: bool = False):
     """Block counts for an uneven batch (tdsolve_batch_autotune: one shared
-    choice of 32 or 64 rows per block, timed on the whole batch).  Cached
-    like autotune(), by device, mode and the digest of the (M, N) list.
-    Returns (list of P, ms per batch solve)."""
+    choice of 32 or 64 rows per block, timed on the whole batch, and the
+    refinement passes of the refined mode chosen by accuracy).  Cached like
+    autotune(), by device, mode and the digest of the (M, N) list.  Returns
+    (list of P, ms per batch solve), or (list of P, passes, ms) with
+    with_passes."""
     m = mode_id(mode)
     K = len(b_list)
     bs = [_host_f64(b) for b in b_list]
@@ -553,20 +563,48 @@ def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
     Ns = np.array([int(n) for n in N_list], dtype=np.int64)
     digest = hashlib.sha256(Ms.tobytes() + Ns.tobytes()).hexdigest()[:16]
     key = f"batch|{_device_key()}|K={K}|MN={digest}|mode={m}"
-    if cache:
-        hit = _cache_load().get(key)
-        if hit is not None:
-            return [int(p) for p in hit["P"]], float(hit["ms"])
-    ap = (ctypes.c_void_p * K)(*[x.ctypes.data for x in as_])
-    bp = (ctypes.c_void_p * K)(*[x.ctypes.data for x in bs])
-    Ps = np.zeros(K, dtype=np.int32)
-    ms = ctypes.c_double()
-    _check(lib().tdsolve_batch_autotune(K, ap, bp, _ptr(Ms), _ptr(Ns), m, int(reps), _ptr(Ps),
-                                        ctypes.byref(ms), _stream_ptr(stream)),
-           "tdsolve_batch_autotune")
-    if cache:
-        _cache_store(key, {"P": Ps.tolist(), "ms": ms.value})
-    return Ps.tolist(), ms.value
+    hit = _cache_load().get(key) if cache else None
+    if hit is not None and "passes" in hit:
+        Pl, passes, ms = [int(p) for p in hit["P"]], int(hit["passes"]), float(hit["ms"])
+    else:
+        ap = (ctypes.c_void_p * K)(*[x.ctypes.data for x in as_])
+        bp = (ctypes.c_void_p * K)(*[x.ctypes.data for x in bs])
+        Ps = np.zeros(K, dtype=np.int32)
+        npass = ctypes.c_int32()
+        msv = ctypes.c_double()
+        _check(lib().tdsolve_batch_autotune(K, ap, bp, _ptr(Ms), _ptr(Ns), m, int(reps),
+                                            _ptr(Ps), ctypes.byref(npass), ctypes.byref(msv),
+                                            _stream_ptr(stream)), "tdsolve_batch_autotune")
+        Pl, passes, ms = Ps.tolist(), int(npass.value), float(msv.value)
+        if cache:
+            _cache_store(key, {"P": Pl, "passes": passes, "ms": ms})
+    return (Pl, passes, ms) if with_passes else (Pl, ms)
+
+
+def autotune_plan(a, b, N: int, mode="f32_refined", P: int = 0, F=None, reps: int = 5,
+                  stream=None):
+    """Measured configuration of a single-matrix plan (tdsolve_autotune_plan):
+    block count (P = 0: chosen; else fixed), interface order, fused order and
+    the refined mode's passes, on the device right-hand sides F ((M, N), the
+    mode's input type) or generated ones.  Returns a dict with P, order
+    ('recurrence' or 'dense'), passes, fuse_lag, fuse_tile, ms, r2."""
+    m = mode_id(mode)
+    b = _host_f64(b)
+    M = int(b.shape[0])
+    a = _host_f64(a) if M > 1 else np.zeros(1)
+    fp = None
+    if F is not None:
+        Plan._check_tensor(None, F, _F_DTYPE[m], "F", rows=M)
+        if F.shape[1] != N:
+            raise ValueError("F must have N columns")
+        fp = ctypes.c_void_p(F.data_ptr())
+    out = Tuning()
+    _check(lib().tdsolve_autotune_plan(_ptr(a), _ptr(b), M, int(N), m, int(P), fp, int(reps),
+                                       ctypes.byref(out), _stream_ptr(stream)),
+           "tdsolve_autotune_plan")
+    return {"P": out.P, "order": {0: "recurrence", 2: "dense"}.get(out.order, "recurrence"),
+            "passes": out.passes, "fuse_lag": out.fuse_lag, "fuse_tile": out.fuse_tile,
+            "ms": out.ms, "r2": out.r2}
 
 
 # Plans of the differentiable solve, reused while a and b are the same

@@ -1,8 +1,10 @@
-"""GPU: the measured block-count choice (tdsolve_autotune,
-tdsolve_batch_autotune) and its JSON cache.  The chosen decomposition is a
-free parameter of the method, so the checks are that the choice is one of
-the candidates, that a plan built with it solves to the oracle's tolerance,
-and that the cache returns the stored choice without measuring again."""
+"""GPU: the measured choices (tdsolve_autotune, tdsolve_autotune_plan,
+tdsolve_batch_autotune) and their JSON cache.  The chosen decomposition,
+interface order and launch order are free parameters of the method, so the
+checks are that each choice is one of the candidates, that a plan built
+with it solves to the oracle's tolerance, that the refinement passes meet
+the stated accuracy rule, and that the cache returns the stored choice
+without measuring again."""
 import json
 
 import numpy as np
@@ -82,3 +84,58 @@ def test_autotune_rejects_bad_arguments():
         t.autotune(a, b, 0, "f64", cache=False)
     with pytest.raises(t.TdsError):
         t.autotune(a, b, 4, 7, cache=False)
+
+
+@pytest.mark.parametrize("mode", ["f32_refined", "f32_wide", "f64"])
+def test_autotune_plan_choice_solves(mode):
+    # the Poisson series (ill-conditioned, P fixed at 64) and its own
+    # right-hand sides: the plan configured as chosen meets the parity gates,
+    # and in the refined mode the chosen passes are the fewest whose residual
+    # stays within twice the FP64-arithmetic solve's
+    from tests import _parity
+    w = wl.poisson_series(M=4096, N=1024, P=64)
+    a, b, F32 = w["a"], w["b"], w["F"]
+    Fs = torch.from_numpy(F32).to(DEV)
+    Fin = Fs.double() if mode == "f64" else Fs
+    tun = t.autotune_plan(a, b, 1024, mode, P=64, F=Fin)
+    print(f"autotune_plan {mode}: {tun}", flush=True)
+    assert tun["P"] == 64 and tun["order"] in ("recurrence", "dense") and tun["ms"] > 0
+    assert (tun["fuse_lag"], tun["fuse_tile"]) in ((0, 0), (8, 512))
+    plan = t.Plan(a, b, 64)
+    plan.set_interface(tun["order"])
+    plan.set_fused(tun["fuse_lag"], tun["fuse_tile"] or 512)
+    if mode == "f32_refined":
+        assert 1 <= tun["passes"] <= 3
+        plan.set_refinement(tun["passes"])
+    else:
+        assert tun["passes"] == 0
+    Xh = plan.solve(Fin, mode=mode).cpu().numpy()
+    Fw = F32.astype(np.float64)
+    ref = oracle.thomas(a, b, Fw)
+    _parity.check(Xh, ref, _parity.tol64(a, b, Fw, ref, 64), f"autotuned poisson {mode}")
+    r2 = _parity.method.residual_columns(a, b, Fw, Xh)["r2"].max()
+    assert abs(r2 - tun["r2"]) <= 1e-3 * r2
+    if mode == "f32_refined":
+        # the rule is applied on a fresh plan (recurrence order, three launches)
+        p0 = t.Plan(a, b, 64)
+        Xw = p0.solve(Fs, mode="f32_wide").cpu().numpy()
+        r2w = _parity.method.residual_columns(a, b, Fw, Xw)["r2"].max()
+        p0.set_refinement(tun["passes"])
+        Xp = p0.solve(Fs, mode=mode).cpu().numpy()
+        assert _parity.method.residual_columns(a, b, Fw, Xp)["r2"].max() <= 2.0 * r2w * (1 + 1e-3)
+        if tun["passes"] > 1:
+            p0.set_refinement(tun["passes"] - 1)
+            Xp = p0.solve(Fs, mode=mode).cpu().numpy()
+            assert _parity.method.residual_columns(a, b, Fw, Xp)["r2"].max() > 2.0 * r2w * (1 - 1e-3)
+
+
+def test_batch_autotune_passes(tmp_path, monkeypatch):
+    monkeypatch.setenv("TDSOLVE_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    w = wl.uneven_batch(seed=9, K=12, M_lo=64, M_hi=3000, N_hi=600)
+    items = w["items"]
+    a_l, b_l = [it["a"] for it in items], [it["b"] for it in items]
+    Ns = [it["N"] for it in items]
+    P_l, passes, ms = t.batch_autotune(a_l, b_l, Ns, "f32_refined", with_passes=True)
+    assert 1 <= passes <= 3 and ms > 0
+    assert t.batch_autotune(a_l, b_l, Ns, "f32_refined", with_passes=True) == (P_l, passes, ms)
+    assert t.batch_autotune(a_l, b_l, Ns, "f64", with_passes=True)[1] == 0

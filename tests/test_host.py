@@ -243,7 +243,16 @@ def test_new_entry_points_reject_bad_arguments_without_gpu():
     assert L.tdsolve_autotune(P_(a), P_(b), 10, 5, 9, 3, ctypes.byref(Pout), ctypes.byref(ms),
                               None) == -1                              # bad mode
     assert L.tdsolve_autotune(P_(a), P_(b), 10, 5, 0, 3, None, None, None) == -1
-    assert L.tdsolve_batch_autotune(0, None, None, None, None, 0, 3, None, None, None) == -1
+    assert L.tdsolve_batch_autotune(0, None, None, None, None, 0, 3, None, None, None,
+                                    None) == -1
+    tun = t.Tuning()
+    assert L.tdsolve_autotune_plan(P_(a), P_(b), 10, 0, 0, 0, None, 3, ctypes.byref(tun),
+                                   None) == -1                         # N = 0
+    assert L.tdsolve_autotune_plan(P_(a), P_(b), 10, 5, 9, 0, None, 3, ctypes.byref(tun),
+                                   None) == -1                         # bad mode
+    assert L.tdsolve_autotune_plan(P_(a), P_(b), 10, 5, 0, -1, None, 3, ctypes.byref(tun),
+                                   None) == -1                         # P < 0
+    assert L.tdsolve_autotune_plan(P_(a), P_(b), 10, 5, 0, 0, None, 3, None, None) == -1
     assert L.tdsolve_set_interface(None, 1) == -1
     assert L.tdsolve_prepare_host_general(P_(a), P_(b), None, 10, 2, None, None, None, None,
                                           None, None) == -1
