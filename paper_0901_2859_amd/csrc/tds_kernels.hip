@@ -330,7 +330,6 @@ __device__ __forceinline__ void beta_rows_item(const DevTables& T, const Fin* __
 // after a barrier.
 constexpr int kScanMaxGroupsSingle = 64;  // single-matrix workgroups (up to 1024 threads)
 constexpr int kScanMaxPer = 8;     // beta values a thread keeps in registers (single)
-constexpr int kScanMaxPerBatch = 16;       // the same in the batch kernel
 constexpr int kChainChunk = 8;     // beta values read per memory round trip
 
 // S^R recurrence y <- rho_j y + beta^R_j for j = j0 .. j1-1 (rho_0 is not
@@ -1308,19 +1307,18 @@ __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict_
 
 // one workgroup of kScanBatchThreads per R_k right-hand sides of matrix k
 // (G_k R_k <= kScanBatchThreads); LDS for the largest shape, G R = 256 with
-// per <= kScanMaxPerBatch
+// per <= kScanMaxPer
 __global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
     const BatchDesc* __restrict__ D, const int32_t* __restrict__ own) {
     // carries 2 G R + factors 2 G + S^R by row G per R, with G R <= 256
     __shared__ double S[2 * kScanBatchThreads + 2 * kScanMaxGroupsSingle +
-                        kScanBatchThreads * kScanMaxPerBatch];
+                        kScanBatchThreads * kScanMaxPer];
     const int64_t item = xcd_item();
     const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
     const int64_t local = item - d.scan0;
     if (d.T.P < 2 || (local << d.lgR) >= d.N) return;   // uniform per workgroup
-    iface_item<kScanMaxPerBatch>(d.T, d.N, d.per, d.G, d.betaR, d.betaL, d.xsep, local, S,
-                                 d.lgR);
+    iface_item<kScanMaxPer>(d.T, d.N, d.per, d.G, d.betaR, d.betaL, d.xsep, local, S, d.lgR);
 }
 
 template <int TMAX, typename Fin, typename Xout, int KIND>
