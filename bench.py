@@ -60,7 +60,7 @@ def parse():
     p.add_argument("--passes", type=int, default=None,
                    help="refinement passes of the f32_refined mode; default: the autotuner's "
                         "(the fewest whose residual on the workload's right-hand sides stays "
-                        "within twice that of the FP64-arithmetic solve)")
+                        "within 1.25 times that of the FP64-arithmetic solve)")
     p.add_argument("--interface", default="auto",
                    choices=["auto", "recurrence", "dichotomy", "dense"],
                    help="evaluation order of the interface values (single-matrix workloads); "

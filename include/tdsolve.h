@@ -33,9 +33,12 @@
  *   TDS_F64          F double, X double; FP64 sweeps.
  *   TDS_F32_REFINED  F float,  X double; FP32 sweeps inside each block with
  *                    FP64 interface values and FP64 residual-based
- *                    refinement passes, all in registers (default 2 passes;
- *                    blocks of more than 64 rows are swept in FP64
- *                    arithmetic instead, as in TDS_F32_WIDE).
+ *                    refinement passes, all in registers: `passes` passes
+ *                    on the block's zero-boundary solution, then (passes >=
+ *                    1) one more on the whole solution with its boundary
+ *                    values (default 2 passes; blocks of more than 64 rows
+ *                    are swept in FP64 arithmetic instead, as in
+ *                    TDS_F32_WIDE).
  *   TDS_F32          F float,  X float;  FP32 sweeps, FP64 interface step.
  *   TDS_F32_WIDE     F float,  X double; FP64 sweeps of the widened input.
  *
@@ -252,7 +255,9 @@ int tdsolve_set_interface(tds_handle h, int32_t order);
  * Errors: TDS_EINVAL (batch handle, lag outside 0..64, a bad tile). */
 int tdsolve_set_fused(tds_handle h, int32_t lag, int32_t tile);
 
-/* Number of refinement passes for TDS_F32_REFINED (0..8; default 2). */
+/* Number of refinement passes for TDS_F32_REFINED (0..8; default 2): FP64
+ * residual passes on each block's zero-boundary solution; with 1 or more, a
+ * last pass follows on the solution with its boundary values. */
 int tdsolve_set_refinement(tds_handle h, int32_t passes);
 
 int tdsolve_info(tds_handle h, tds_info* info);
@@ -328,8 +333,8 @@ typedef struct {
  * three interleaved rounds of `reps` calls (<= 0: 5), keeping its fastest
  * round.  For TDS_F32_REFINED the refinement passes of each block count are
  * fixed first, by accuracy: the fewest (1..3) whose largest relative
- * residual on F is within twice that of the same plan's TDS_F32_WIDE solve
- * (FP64 arithmetic).  Allocates and frees device memory and synchronises
+ * residual on F is within 1.25 times that of the same plan's TDS_F32_WIDE
+ * solve (FP64 arithmetic).  Allocates and frees device memory and synchronises
  * `stream`.  Errors: as tdsolve_prepare, TDS_EINVAL (N < 1, P < 0, bad mode,
  * NULL out), TDS_ENOMEM, TDS_EHIP. */
 int tdsolve_autotune_plan(const double* a, const double* b, int64_t M, int64_t N,
@@ -371,8 +376,8 @@ int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
  * written to P_out (K entries), the milliseconds per call to *ms_out (may be
  * NULL).  For TDS_F32_REFINED, *passes_out (may be NULL; 0 in other modes)
  * receives the fewest refinement passes (1..3) whose largest normwise
- * backward error (tdsolve_status) stays within twice that of the same batch
- * solved in FP64 arithmetic (TDS_F32_WIDE).  Allocation, synchronisation and
+ * backward error (tdsolve_status) stays within 1.25 times that of the same
+ * batch solved in FP64 arithmetic (TDS_F32_WIDE).  Allocation, synchronisation and
  * errors as tdsolve_autotune. */
 int tdsolve_batch_autotune(int32_t K, const double* const* a,
                            const double* const* b, const int64_t* M,

@@ -60,6 +60,17 @@ struct DevTables {
     // tables of a half-block partition (half_tables): entry 2j+1 holds
     // 1 / (Schur complement of block j's middle row); P entries
     double* mid_inv = nullptr;
+    // twisted elimination of a half-block partition (half_tables), in
+    // slots k = 0..kHalfRows-1 of half h of block j at (2j + h) kHalfRows + k:
+    // the left half's rows top-down, the right half's bottom-up (padding
+    // slots first when it is shorter); s: coupling to the previous slot's
+    // row, r: 1 / pivot, c: coupling to the next slot's row (m after the
+    // last slot) times r, e: eliminated response to the outer boundary
+    // value
+    double* tw_s = nullptr;
+    double* tw_r = nullptr;
+    double* tw_c = nullptr;
+    double* tw_e = nullptr;
 };
 
 // Host-side FP64 preliminary step.  Returns a tds_status code.
@@ -74,6 +85,7 @@ struct HostTables {
     std::vector<double> l64;               // sub-diagonal (a copy of a64 if symmetric)
     int32_t general = 0;                   // 1: non-symmetric A (by similarity)
     std::vector<double> mid_inv;           // half-block partitions only (half_tables)
+    std::vector<double> tw_s, tw_r, tw_c, tw_e;   // half-block partitions: twisted slots
 };
 
 int host_prepare(const double* a, const double* b, int64_t M, int32_t P,

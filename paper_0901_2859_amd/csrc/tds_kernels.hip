@@ -720,6 +720,59 @@ __device__ __forceinline__ void refined_solve(const DevTables& T, int64_t i0,
     }
 }
 
+// The last residual pass of the refined sweep, over a block (or half
+// block) of cnt rows whose boundary values are known: xL beside its first
+// row (coupling cl) and xR beside row cnt-1 (coupling cr); x holds the
+// block's values including the boundary responses.  The residual is formed
+// in FP64 with the boundary terms, eliminated in FP32 as in the other
+// passes, and the back substitution carries each row's rounded update into
+// the next row in FP64:
+//     y_r = x_r + (w_r - cp_r (y_{r+1} - x_{r+1})),
+// so the result is the solution of the bidiagonal system U y = U x + w up
+// to one rounding per row, as in a direct sweep: its rounding errors stay
+// correlated along the block instead of adding an independent error to
+// every row (which would raise the residual by about the ratio of |A| to
+// the elimination's lower factor).
+template <int TMAX, bool GEN, int STRIDE = kWG>
+__device__ __forceinline__ void refined_boundary_pass(const DevTables& T, int64_t i0,
+                                                      const float* __restrict__ my_f, int cnt,
+                                                      double cl, double xL, double cr, double xR,
+                                                      double (&x)[TMAX]) {
+    asm volatile("" ::: "memory");
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    const cptr<double> in64p = cst(T.in64 + i0) + z;
+    const cptr<double> inl64p = GEN ? cst(T.inl64 + i0) + z : in64p;
+    const cptr<double> b64p = cst(T.b64 + i0) + z;
+    const cptr<float> inl32p = cst((GEN ? T.inl32 : T.in32) + i0) + z;
+    const cptr<float> cp32p = cst(T.cp32 + i0) + z, rd32p = cst(T.rd32 + i0) + z;
+    float w[TMAX];
+#pragma unroll
+    for (int r = 0; r < TMAX; ++r) {
+        if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+        double res = (double)my_f[r * STRIDE] - b64p[r] * x[r];
+        if (r > 0) res -= inl64p[r - 1] * x[r - 1];
+        if (r + 1 < TMAX) res -= in64p[r] * x[r + 1];
+        if (r == 0) res -= cl * xL;
+        if (r == cnt - 1) res -= cr * xR;
+        const float prev = (r > 0) ? w[r - 1] : 0.0f;
+        const float sub = (r > 0) ? inl32p[r - 1] : 0.0f;
+        w[r] = ((float)res - sub * prev) * rd32p[r];
+    }
+    double carry = 0.0;
+#pragma unroll
+    for (int r = TMAX - 1; r >= 0; --r) {
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        // converted here, not beside the elimination (which would hold
+        // every row's w in FP64)
+        float wr = w[r];
+        asm volatile("" : "+v"(wr));
+        const double y = x[r] + fma(-(double)cp32p[r], carry, (double)wr);
+        carry = y - x[r];
+        x[r] = y;
+    }
+}
+
 template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
 __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restrict__ xb, int lane,
                                            int64_t N, int cnt, double cl, double xl, double cr,
@@ -781,11 +834,15 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
 #pragma unroll
         for (int r = 0; r < TMAX; ++r) my_f[r * kWG] = (float)f[r];
         double x[TMAX];
+        // after the zero-boundary passes, one more over the whole solution
+        // with its boundary values (refined_boundary_pass)
         refined_solve<TMAX, GEN>(T, i0, my_f, passes, x);
 #pragma unroll
+        for (int r = 0; r < TMAX; ++r) x[r] = fma(xr, vv[r], fma(xl, uu[r], x[r]));
+        if (passes >= 1) refined_boundary_pass<TMAX, GEN>(T, i0, my_f, cnt, cl, xl, cr, xr, x);
+#pragma unroll
         for (int r = 0; r < TMAX; ++r)
-            if (r < cnt)
-                store_x(&(xb + (int64_t)r * N)[lane], (Xout)fma(xr, vv[r], fma(xl, uu[r], x[r])));
+            if (r < cnt) store_x(&(xb + (int64_t)r * N)[lane], (Xout)x[r]);
     }
 }
 
@@ -861,10 +918,12 @@ __device__ __forceinline__ void sweep_stream_item(const DevTables& T, const Fin*
 
 // Occupancy target (waves per SIMD) of the refined sweep, which holds about
 // 3 registers per row (x in FP64, the FP32 elimination value; F sits in
-// LDS); the other sweeps are left to the compiler.
+// LDS): 4 up to 32 rows (the last pass with boundary values needs a few
+// more than 128 registers otherwise), 2 up to 64; the other sweeps are left
+// to the compiler.
 template <int KIND, int TMAX>
 constexpr int sweep_min_waves() {
-    return TMAX > 64 ? 1 : KIND == kSweepRefined ? 2 : 1;
+    return TMAX > 64 ? 1 : KIND == kSweepRefined ? (TMAX <= 32 ? 4 : 2) : 1;
 }
 
 // ==========================================================================
@@ -915,14 +974,27 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 // kHalfRows rows, the middle row m = i0 + kHalfRows and a right half
 // m+1..i1.  Wavefronts 0-1 take the left half of 128 right-hand sides,
 // wavefronts 2-3 the right half of the same ones (RHS = 128; with RHS =
-// 256, 8 wavefronts of which 0-3 take the left half); each half is solved
-// with zero boundary values (refined_solve, or one FP64 sweep).  The value
-// at m then follows from row m's equation with its neighbours
-// written by superposition (x_{m-1} through the left half, x_{m+1} through
-// the right one):
+// 256, 8 wavefronts of which 0-3 take the left half).
+//
+// FP64 arithmetic (kSweep64): a twisted factorization of the block, the
+// left half eliminated top-down and the right half bottom-up, each with its
+// outer boundary value moved into the eliminated right-hand side; row m's
+// equation then gives
+//     x_m = (f_m - A[m][m-1] dA_{m-1} - A[m][m+1] dB_{m+1}) mid_inv,
+// and each half back-substitutes outward from m.  This is a backward-stable
+// elimination of the block with known boundary values, like the
+// whole-block sweep: its rounding errors stay correlated along the block,
+// and the residual stays at the whole-block sweep's level.
+//
+// Refined (kSweepRefined): each half is solved with zero boundary values
+// (refined_solve) and the boundary values enter by superposition:
 //     x_m = (f_m - A[m][m-1] qA - A[m][m+1] qB) mid_inv,
-//     qA = x0_{m-1} + x(s_j) u_{m-1},  qB = x0_{m+1} + x(s_{j+1}) v_{m+1},
-// where each half contributes its term through LDS and both evaluate the
+//     qA = x0_{m-1} + x(s_j) u_{m-1},  qB = x0_{m+1} + x(s_{j+1}) v_{m+1};
+// after the zero-boundary passes one more pass runs on each half with its
+// boundary values (refined_boundary_pass, when passes >= 1), so that the
+// rounding of the superposition does not stay in the residual.
+//
+// Each half contributes its term to x_m through LDS and both evaluate the
 // same expression (bitwise the same x_m).  Each lane keeps half the rows of
 // the whole-block sweep: 4 wavefronts per SIMD instead of 2, which overlap
 // their loads, passes and stores.
@@ -978,8 +1050,20 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
         if (h == 0 && j > 0) xo = xsep[(int64_t)(j - 1) * N + n0 + lane];
         if (h == 1 && j < P - 1) xo = xsep[(int64_t)j * N + n0 + lane];
     }
+    // FP64: slot k of the twisted elimination (tw_* tables) is row i0 + k
+    // on the left and row i0 + TM - 1 - k on the right, whose padding slots
+    // (k < TM - cnt) re-read its last row
+    const int64_t sb = ((int64_t)2 * j + h) * TM;
     Fin f[TM];
-    sweep_load<TM, Fin>(F + i0 * N + n0, lane, N, cnt, f);
+    if constexpr (KIND == kSweepRefined) {
+        sweep_load<TM, Fin>(F + i0 * N + n0, lane, N, cnt, f);
+    } else {
+#pragma unroll
+        for (int k = 0; k < TM; ++k) {
+            const int o = h ? (TM - 1 - k < cnt ? TM - 1 - k : cnt - 1) : k;
+            f[k] = (F + (i0 + o) * N + n0)[lane];
+        }
+    }
     double fm = 0.0;
     if (h == 0) fm = (double)(F + seg_hi * N + n0)[lane];     // row m
     double x[TM];
@@ -989,18 +1073,16 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
         for (int r = 0; r < TM; ++r) my_f[r * NT] = f[r];
         refined_solve<TM, GEN, NT>(H, i0, my_f, passes, x);
     } else {
-        // zero-boundary FP64 sweep of the half; rows past cnt come after the
-        // last real row, whose elimination factor is zero
-        const cptr<double> l64 = cst((GEN ? H.l64 : H.a64) + i0);
-        const cptr<double> cp64 = cst(H.cp64 + i0), rd64 = cst(H.rd64 + i0);
+        // FP64: the twisted elimination toward the middle row, in slot
+        // order (x holds the eliminated right-hand side d); a padding slot's
+        // successor has coupling zero, so padding never reaches a real row
+        const cptr<double> ts = cst(H.tw_s + sb), tr = cst(H.tw_r + sb);
 #pragma unroll
-        for (int r = 0; r < TM; ++r) {
-            const double prev = (r > 0) ? x[r - 1] : 0.0;
-            const double sub = (r > 0) ? l64[r - 1] : 0.0;
-            x[r] = ((double)f[r] - sub * prev) * rd64[r];
+        for (int k = 0; k < TM; ++k) {
+            const double prev = (k > 0) ? x[k - 1] : 0.0;
+            const double sub = (k > 0) ? ts[k] : 0.0;
+            x[k] = ((double)f[k] - sub * prev) * tr[k];
         }
-#pragma unroll
-        for (int r = TM - 2; r >= 0; --r) x[r] -= cp64[r] * x[r + 1];
     }
     if constexpr (Wait::kFused) {
         if (!__syncthreads_and(early)) {         // one decision for the workgroup
@@ -1010,19 +1092,52 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
         }
     }
     const cptr<double> uu = cst(H.u + i0), vv = cst(H.v + i0);
-    if (h == 0)
-        s_q[c] = fm - cst(GEN ? H.l64 : H.a64)[seg_hi - 1] * fma(xo, uu[TM - 1], x[TM - 1]);
-    else
-        s_q[RHS + c] = fma(xo, vv[0], x[0]);
+    if constexpr (KIND == kSweepRefined) {
+        // each half's end value next to m in terms of its outer boundary
+        if (h == 0)
+            s_q[c] = fm - cst(GEN ? H.l64 : H.a64)[seg_hi - 1] * fma(xo, uu[TM - 1], x[TM - 1]);
+        else
+            s_q[RHS + c] = fma(xo, vv[0], x[0]);
+    } else {
+        // the outer boundary value enters the eliminated right-hand side
+        const cptr<double> te = cst(H.tw_e + sb);
+#pragma unroll
+        for (int k = 0; k < TM; ++k) x[k] = fma(xo, te[k], x[k]);
+        if (h == 0)
+            s_q[c] = fm - cst(GEN ? H.l64 : H.a64)[seg_hi - 1] * x[TM - 1];
+        else
+            s_q[RHS + c] = x[TM - 1];
+    }
     __syncthreads();
     const int64_t m = cst(H.starts)[2 * j + 1];
     const double xm = (s_q[c] - cst(H.a64)[m] * s_q[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
     if (!live) return;
-    const double xl = h ? xm : xo, xr = h ? xo : xm;
     double* xb = X + i0 * N + n0;
+    if constexpr (KIND == kSweepRefined) {
+        // superposition, then (one or more passes) a pass over the half
+        // with its boundary values x(s_j), x_m or x_m, x(s_{j+1})
+        const double xl = h ? xm : xo, xr = h ? xo : xm;
 #pragma unroll
-    for (int r = 0; r < TM; ++r)
-        if (r < cnt) store_x(&(xb + (int64_t)r * N)[c], fma(xr, vv[r], fma(xl, uu[r], x[r])));
+        for (int r = 0; r < TM; ++r) x[r] = fma(xr, vv[r], fma(xl, uu[r], x[r]));
+        if (passes >= 1) {
+            const double cl = (h == 0 && j == 0) ? 0.0 : cst(GEN ? H.l64 : H.a64)[i0 - 1];
+            const double cr = cst(H.a64)[seg_hi - 1];      // zero past the last row
+            refined_boundary_pass<TM, GEN, NT>(H, i0, s_f + threadIdx.x, cnt, cl, xl, cr, xr, x);
+        }
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+            if (r < cnt) store_x(&(xb + (int64_t)r * N)[c], x[r]);
+    } else {
+        // back substitution outward from m, slots TM-1 .. 0
+        const cptr<double> tc = cst(H.tw_c + sb);
+        double y = xm;
+#pragma unroll
+        for (int k = TM - 1; k >= 0; --k) {
+            y = fma(-tc[k], y, x[k]);
+            const int o = h ? TM - 1 - k : k;
+            if (o < cnt) store_x(&(xb + (int64_t)o * N)[c], y);
+        }
+    }
     if (h == 0) {
         store_x(&X[m * N + n0 + c], xm);
         if (j > 0) store_x(&X[seg_lo * N + n0 + c], xo);

@@ -337,6 +337,11 @@ int half_tables(const HostTables& o, int32_t lead, HostTables& h) {
     // (1/16 of its terms on the Poisson matrix): it is formed from the
     // halves' extended-precision responses, not from their FP64 tables
     h.mid_inv.assign(h.P, 0.0);
+    const size_t slots = 2 * (size_t)P * (size_t)lead;
+    h.tw_s.assign(slots, 0.0);
+    h.tw_r.assign(slots, 1.0);
+    h.tw_c.assign(slots, 0.0);
+    h.tw_e.assign(slots, 0.0);
     std::vector<wide> cp, rd, u, v;
     for (int32_t j = 0; j < P; ++j) {
         const int64_t m = h.starts[2 * j + 1];
@@ -361,6 +366,35 @@ int half_tables(const HostTables& o, int32_t lead, HostTables& h) {
         const wide den = (wide)bb[m] + (wide)lo[m - 1] * vA + (wide)up[m] * uB;
         if (den == 0.0L || bad((double)den)) return TDS_ESINGULAR;
         h.mid_inv[2 * j + 1] = (double)(1.0L / den);
+        // twisted elimination toward m, in slots k = 0..lead-1 of each half:
+        // the left half top-down (slot k = row a0 + k), the right half
+        // bottom-up (slot k = row m + lead - k; slots before its last row
+        // b1 are padding: s = c = e = 0, r = 1).  Per slot: s, the coupling
+        // to the previous slot's row; r, 1 / pivot; c, the coupling to the
+        // next slot's row (the last slot's next row is m) times r; e, the
+        // eliminated response to the block's outer boundary value.
+        for (int hh = 0; hh < 2; ++hh) {
+            const size_t base = ((size_t)2 * j + hh) * (size_t)lead;
+            wide c = 0.0L, e = 0.0L;
+            bool first = true;
+            for (int32_t k = 0; k < lead; ++k) {
+                const int64_t i = hh == 0 ? a0 + k : m + lead - k;
+                if (hh == 1 && i > b1) continue;                       // padding slot
+                const wide sk = first ? 0.0L : (wide)(hh == 0 ? lo[i - 1] : up[i]);
+                const wide d = (wide)bb[i] - sk * c;
+                if (d == 0.0L || bad((double)d)) return TDS_ESINGULAR;
+                const wide r = 1.0L / d;
+                const wide outer = hh == 0 ? (j > 0 ? (wide)lo[a0 - 1] : 0.0L)
+                                           : (j < P - 1 ? (wide)up[b1] : 0.0L);
+                e = (first ? -outer : -sk * e) * r;
+                c = (wide)(hh == 0 ? up[i] : lo[i - 1]) * r;
+                h.tw_s[base + k] = (double)sk;
+                h.tw_r[base + k] = (double)r;
+                h.tw_c[base + k] = (double)c;
+                h.tw_e[base + k] = (double)e;
+                first = false;
+            }
+        }
     }
     return TDS_OK;
 }

@@ -86,12 +86,15 @@ def test_autotune_rejects_bad_arguments():
         t.autotune(a, b, 4, 7, cache=False)
 
 
+SLACK = 1.25     # the autotuner's passes rule: residual within this factor of FP64 arithmetic's
+
+
 @pytest.mark.parametrize("mode", ["f32_refined", "f32_wide", "f64"])
 def test_autotune_plan_choice_solves(mode):
     # the Poisson series (ill-conditioned, P fixed at 64) and its own
     # right-hand sides: the plan configured as chosen meets the parity gates,
     # and in the refined mode the chosen passes are the fewest whose residual
-    # stays within twice the FP64-arithmetic solve's
+    # stays within 1.25 times the FP64-arithmetic solve's
     from tests import _parity
     w = wl.poisson_series(M=4096, N=1024, P=64)
     a, b, F32 = w["a"], w["b"], w["F"]
@@ -122,11 +125,11 @@ def test_autotune_plan_choice_solves(mode):
         r2w = _parity.method.residual_columns(a, b, Fw, Xw)["r2"].max()
         p0.set_refinement(tun["passes"])
         Xp = p0.solve(Fs, mode=mode).cpu().numpy()
-        assert _parity.method.residual_columns(a, b, Fw, Xp)["r2"].max() <= 2.0 * r2w * (1 + 1e-3)
+        assert _parity.method.residual_columns(a, b, Fw, Xp)["r2"].max() <= SLACK * r2w * (1 + 1e-3)
         if tun["passes"] > 1:
             p0.set_refinement(tun["passes"] - 1)
             Xp = p0.solve(Fs, mode=mode).cpu().numpy()
-            assert _parity.method.residual_columns(a, b, Fw, Xp)["r2"].max() > 2.0 * r2w * (1 - 1e-3)
+            assert _parity.method.residual_columns(a, b, Fw, Xp)["r2"].max() > SLACK * r2w * (1 - 1e-3)
 
 
 def test_batch_autotune_passes(tmp_path, monkeypatch):
