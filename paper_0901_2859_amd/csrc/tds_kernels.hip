@@ -414,11 +414,28 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
 
     double yl = 0.0, pr = 1.0, zl = 0.0, pl = 1.0;
     double bRv[MAXPER], bLv[MAXPER];
+    double rv[MAXPER], lv[MAXPER];     // the group's factors (keep path)
     const bool keep = per <= MAXPER;
     if (grp) {
-        // the products of the factors do not depend on the right-hand side
-        for (int32_t j = f0; j < f1; ++j) pr *= (j > 0) ? rho[j] : 0.0;
-        for (int32_t j = b1; j > b0; --j) pl *= (j < P - 1) ? lam[j] : 0.0;
+        // the products of the factors do not depend on the right-hand side;
+        // on the keep path every factor is loaded at once (one round trip)
+        // and kept for the recurrences
+        if (keep) {
+#pragma unroll
+            for (int u = 0; u < MAXPER; ++u) {
+                const int32_t jf = f0 + u, jb = b1 - u;
+                rv[u] = (jf < f1 && jf > 0) ? rho[jf] : 0.0;
+                lv[u] = (jb > b0 && jb < P - 1) ? lam[jb] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < MAXPER; ++u) {
+                if (f0 + u < f1) pr *= rv[u];
+                if (b1 - u > b0) pl *= lv[u];
+            }
+        } else {
+            for (int32_t j = f0; j < f1; ++j) pr *= (j > 0) ? rho[j] : 0.0;
+            for (int32_t j = b1; j > b0; --j) pl *= (j < P - 1) ? lam[j] : 0.0;
+        }
     }
     if (live) {
         if (keep) {
@@ -431,8 +448,8 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
 #pragma unroll
             for (int u = 0; u < MAXPER; ++u) {
                 const int32_t jf = f0 + u, jb = b1 - u;
-                if (jf < f1) yl = fma((jf > 0) ? rho[jf] : 0.0, yl, bRv[u]);
-                if (jb > b0) zl = fma((jb < P - 1) ? lam[jb] : 0.0, zl, bLv[u]);
+                if (jf < f1) yl = fma(rv[u], yl, bRv[u]);
+                if (jb > b0) zl = fma(lv[u], zl, bLv[u]);
             }
         } else {
             yl = chain_right<COH>(yl, rho, betaR, N, n, f0, f1, nullptr);
@@ -464,7 +481,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
             for (int u = 0; u < MAXPER; ++u) {
                 const int32_t j = f0 + u;
                 if (j < f1) {
-                    y = fma((j > 0) ? rho[j] : 0.0, y, bRv[u]);
+                    y = fma(rv[u], y, bRv[u]);
                     sr[j * R + lane] = y;
                 }
             }
@@ -480,7 +497,7 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
         for (int u = 0; u < MAXPER; ++u) {
             const int32_t j = b1 - u;
             if (j > b0) {
-                z = fma((j < P - 1) ? lam[j] : 0.0, z, bLv[u]);
+                z = fma(lv[u], z, bLv[u]);
                 st_w<COH>(&xsep[(int64_t)(j - 1) * N + n], sr[(j - 1) * R + lane] + z);   // S^R_j + S^L_j
             }
         }
