@@ -469,9 +469,30 @@ __device__ __forceinline__ void iface_item(const DevTables& T, int64_t N, int32_
     }
     __syncthreads();
     double yin = 0.0, zin = 0.0;
-    for (int q = 0; q < g && q < G; ++q) {
-        yin = fma(prod[q], yin, carry[q * R + lane]);
-        zin = fma(prod[G + q], zin, carry[(G + q) * R + lane]);
+    {
+        // the carries of the groups before this one, in group order; LDS
+        // reads four groups at a time, so that one wait covers four steps
+        const int ng = g < G ? g : G;
+        int q = 0;
+        for (; q + 4 <= ng; q += 4) {
+            double py[4], cy[4], pz[4], cz[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                py[u] = prod[q + u];
+                cy[u] = carry[(q + u) * R + lane];
+                pz[u] = prod[G + q + u];
+                cz[u] = carry[(G + q + u) * R + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                yin = fma(py[u], yin, cy[u]);
+                zin = fma(pz[u], zin, cz[u]);
+            }
+        }
+        for (; q < ng; ++q) {
+            yin = fma(prod[q], yin, carry[q * R + lane]);
+            zin = fma(prod[G + q], zin, carry[(G + q) * R + lane]);
+        }
     }
     // finish the forward group: y_j = S^R_{j+1} into LDS or xsep
     if (live) {
