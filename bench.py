@@ -334,10 +334,12 @@ class Batch:
         self.unknowns = sum(m * n for m, n in zip(self.Ms, self.Ns))
         self.name = ("uneven batch: 256 matrices, M log-uniform [128, 16384], b = 2 + U[0.01, 1], "
                      "a = -1, N uniform [1, 2048], FP32 storage")
+        # matrices per register row bucket (32 or 64 rows per block)
+        per_bucket = {"32": sum(1 for m, p in zip(self.Ms, self.P) if -(-m // p) <= 32)}
+        per_bucket["64"] = len(self.P) - per_bucket["32"]
         self.config = {"workload": self.name, "K": len(self.items), "unknowns": self.unknowns,
-                       "rows_per_block": max(-(-m // p) for m, p in zip(self.Ms, self.P)),
-                       "tuning": {"rows_per_block": max(-(-m // p) for m, p in
-                                                        zip(self.Ms, self.P)),
+                       "matrices_by_rows_per_block": per_bucket,
+                       "tuning": {"matrices_by_rows_per_block": per_bucket,
                                   "passes": tuned_passes, "ms": self.tune_ms}}
 
     def sweep_bytes(self, mode):
@@ -541,9 +543,19 @@ def workload_report(name, args, t, wl, torch, dev, mode, steps, warmup, passes=N
     achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
     batched = name in ("batch", "fourier")
     if batched:
-        rows = max(-(-m // p) for m, p in zip(W.Ms, W.P)) if name == "batch" else 0
+        # the batch sweeps one launch per register row bucket (32, 64 rows);
+        # the phase time covers both when the autotuner mixed them
+        buckets = sorted({32 if -(-m // p) <= 32 else 64 for m, p in zip(W.Ms, W.P)}) \
+            if name == "batch" else [0]
+        if name == "batch":
+            by = {r: sum(m * n for m, n, p in zip(W.Ms, W.Ns, W.P)
+                         if (32 if -(-m // p) <= 32 else 64) == r) for r in buckets}
+            rows = max(by, key=by.get)
+        else:
+            rows = 0
         kname = "k_sweep_batch_halves" if rows == 64 and mode != "f32" else "k_sweep_batch"
-        shape = f"{name}_r{rows}" if name == "batch" else name
+        shape = (f"{name}_r{rows}" if len(buckets) == 1 else f"{name}_mixed") \
+            if name == "batch" else name
     elif mode != "f32" and W.plan.info().sweep_halves:
         kname = "k_sweep_halves"
         shape = f"{name}_{W.M}x{W.N}_P{W.P}"

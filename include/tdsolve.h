@@ -367,18 +367,21 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a,
 int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
                          const int64_t* N, int32_t mode, void* stream);
 
-/* Measured block counts for a batch.  The batch kernels hold every block
- * in one common register row bucket, so the choice is the rows per block,
- * 32 or 64 (64: the sweeps take the blocks in halves), shared by all
- * matrices (P[k] = ceil(M[k] / rows) within the method's limits); each
- * choice is timed on tdsolve_batch_series with N[k] device-generated
- * right-hand sides in three interleaved rounds, and the fastest P[k] are
- * written to P_out (K entries), the milliseconds per call to *ms_out (may be
- * NULL).  For TDS_F32_REFINED, *passes_out (may be NULL; 0 in other modes)
- * receives the fewest refinement passes (1..3) whose largest normwise
- * backward error (tdsolve_status) stays within 1.25 times that of the same
- * batch solved in FP64 arithmetic (TDS_F32_WIDE).  Allocation, synchronisation and
- * errors as tdsolve_autotune. */
+/* Measured block counts for a batch.  Each matrix gets 32 or 64 rows per
+ * block (P[k] = ceil(M[k] / rows) within the method's limits; the batch
+ * runs one launch of each kernel per register row bucket, and with 64 rows
+ * the sweeps take the blocks in halves).  First the same rows for every
+ * matrix, both choices timed on tdsolve_batch_series with N[k]
+ * device-generated right-hand sides in three interleaved rounds; then the
+ * matrices in four classes of equal count by M[k] N[k], largest first: each
+ * class's rows are flipped and kept when the batch is faster (the current
+ * and the flipped batch timed in alternation).  The chosen P[k] go to P_out
+ * (K entries), the milliseconds per call to *ms_out (may be NULL).  For
+ * TDS_F32_REFINED, *passes_out (may be NULL; 0 in other modes) receives the
+ * fewest refinement passes (1..3) whose largest normwise backward error
+ * (tdsolve_status) stays within 1.25 times that of the same batch solved in
+ * FP64 arithmetic (TDS_F32_WIDE).  Allocation, synchronisation and errors as
+ * tdsolve_autotune. */
 int tdsolve_batch_autotune(int32_t K, const double* const* a,
                            const double* const* b, const int64_t* M,
                            const int64_t* N, int32_t mode, int32_t reps,

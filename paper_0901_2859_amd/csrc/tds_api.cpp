@@ -39,10 +39,11 @@ struct tds_plan {
     size_t events_used = 0;
     // batch handles: K matrices sharing one table allocation
     bool is_batch = false;
-    int32_t bucket = 0;                  // common register-sweep row bucket
+    std::vector<int32_t> buckets;        // register-sweep row bucket (32, 64) of each matrix
     std::vector<HostTables> hosts;
     std::vector<DevTables> devs;
-    std::vector<DevTables> devs_h;       // half-block tables, when every matrix has them
+    std::vector<DevTables> devs_h;       // half-block tables of the 64-row matrices, when
+                                         //   every one of them has them
     std::vector<BatchDesc> desc;         // last descriptors uploaded
     BatchDesc* d_desc = nullptr;         // descriptors, then the item owner maps
     size_t desc_bytes = 0;               // capacity of d_desc
@@ -772,33 +773,38 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a, const double* const
     if (!h) return TDS_ENOMEM;
     h->is_batch = true;
     h->hosts.resize(K);
-    int32_t bucket = 0;
+    h->buckets.assign(K, 0);
+    bool any64 = false;
     for (int32_t k = 0; k < K; ++k) {
         int rc = host_prepare(a[k], b[k], M[k], P ? P[k] : 0, h->hosts[k]);
         if (rc) { delete h; return rc; }
         const int32_t bk = rows_bucket(h->hosts[k].max_rows);
         if (bk == 0 || bk > 64) { delete h; return TDS_EUNSUPPORTED; }   // blocks > 64 rows
-        bucket = std::max(bucket, bk);
+        h->buckets[k] = bk;
+        any64 = any64 || bk == 64;
     }
-    h->bucket = bucket;
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return TDS_EHIP; }
     std::vector<unsigned char> img;
     h->devs.resize(K);
-    for (int32_t k = 0; k < K; ++k) h->devs[k] = append_image(h->hosts[k], bucket, img);
-    // 64-row bucket: the sweeps with FP64 results take the blocks in halves
-    // when every matrix's blocks fit them (one sweep kernel for the batch)
-    h->has_halves = bucket == 64;
-    std::vector<HostTables> hh(h->has_halves ? K : 0);
+    for (int32_t k = 0; k < K; ++k) h->devs[k] = append_image(h->hosts[k], h->buckets[k], img);
+    // matrices of the 64-row bucket: the sweeps with FP64 results take the
+    // blocks in halves when every one of them fits them (one sweep kernel
+    // per bucket)
+    h->has_halves = any64;
+    std::vector<HostTables> hh(K);
     for (int32_t k = 0; k < K && h->has_halves; ++k)
-        h->has_halves = half_tables(h->hosts[k], kHalfRows, hh[k]) == TDS_OK;
+        if (h->buckets[k] == 64)
+            h->has_halves = half_tables(h->hosts[k], kHalfRows, hh[k]) == TDS_OK;
     if (h->has_halves) {
         h->devs_h.resize(K);
-        for (int32_t k = 0; k < K; ++k) h->devs_h[k] = append_image(hh[k], 0, img);
+        for (int32_t k = 0; k < K; ++k)
+            if (h->buckets[k] == 64) h->devs_h[k] = append_image(hh[k], 0, img);
     }
     int rc = upload_image(img, &h->dev_mem);
     if (rc) { delete h; return rc; }
     for (int32_t k = 0; k < K; ++k) rebase(h->devs[k], h->dev_mem);
-    for (auto& d : h->devs_h) rebase(d, h->dev_mem);
+    for (int32_t k = 0; k < (int32_t)h->devs_h.size(); ++k)
+        if (h->buckets[k] == 64) rebase(h->devs_h[k], h->dev_mem);
     *out = h;
     return TDS_OK;
 }
@@ -807,10 +813,12 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
                          int32_t mode, void* stream) {
     if (!h || !h->is_batch || !F || !X || !N || !valid_mode(mode)) return TDS_EINVAL;
     const int32_t K = (int32_t)h->devs.size();
-    // work buffer slices and work-item ranges of every matrix
+    // work buffer slices and work-item ranges of every matrix; the beta and
+    // sweep items of the 32-row matrices come first, then those of the
+    // 64-row ones, each group numbered from 0 (one launch per group)
     std::vector<BatchDesc> desc(K);
     size_t bytes = 0;
-    int64_t items = 0, scans = 0;
+    int64_t grp_items[2] = {0, 0}, scans = 0;
     for (int32_t k = 0; k < K; ++k) {
         const DevTables& t = h->devs[k];
         const int64_t n = N[k];
@@ -824,8 +832,9 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         d.X = X[k];
         d.N = n;
         d.T = t;
-        d.H = h->has_halves ? h->devs_h[k] : DevTables();
-        d.item0 = items;
+        const int grp = h->buckets[k] == 64 ? 1 : 0;
+        d.H = (h->has_halves && grp == 1) ? h->devs_h[k] : DevTables();
+        d.item0 = grp_items[grp];
         d.scan0 = scans;
         batch_scan_shape(t.P, &d.per, &d.G, &d.lgR);
         d.pad_ = 0;
@@ -835,10 +844,11 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         d.xsep = (double*)(bytes + 2 * nb);
         bytes += 2 * nb + align256(sizeof(double) * (size_t)(t.P > 1 ? t.P - 1 : 1) * (size_t)n);
         if (n > 0) {
-            items += (int64_t)t.P * ((n + kWG - 1) / kWG);
+            grp_items[grp] += (int64_t)t.P * ((n + kWG - 1) / kWG);
             if (t.P > 1) scans += (n + ((int64_t)1 << d.lgR) - 1) >> d.lgR;
         }
     }
+    const int64_t items = grp_items[0] + grp_items[1];
     if (items == 0) {
         remember(h, F, X, N, K, mode);
         return TDS_OK;
@@ -875,7 +885,8 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
             const BatchDesc& d = desc[k];
             if (d.N == 0) continue;
             const int64_t ni = (int64_t)d.T.P * ((d.N + kWG - 1) / kWG);
-            for (int64_t i = 0; i < ni; ++i) oi[d.item0 + i] = k;
+            const int64_t base = h->buckets[k] == 64 ? grp_items[0] : 0;
+            for (int64_t i = 0; i < ni; ++i) oi[base + d.item0 + i] = k;
             if (d.T.P > 1) {
                 const int64_t ns = (d.N + ((int64_t)1 << d.lgR) - 1) >> d.lgR;
                 for (int64_t i = 0; i < ns; ++i) os[d.scan0 + i] = k;
@@ -902,8 +913,8 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     KTime* tm = timing_slot(h);
     if (h->timing && !tm) return TDS_EHIP;
     if (tm && scans == 0) empty_phase(h, 1);
-    if (launch_batch(h->d_desc, own_items, own_scans, items, scans, h->bucket, mode, h->passes,
-                     h->has_halves, tm, (hipStream_t)stream) != hipSuccess)
+    if (launch_batch(h->d_desc, own_items, own_scans, grp_items[0], grp_items[1], scans, mode,
+                     h->passes, h->has_halves, tm, (hipStream_t)stream) != hipSuccess)
         return TDS_EHIP;
     remember(h, F, X, N, K, mode);
     return TDS_OK;

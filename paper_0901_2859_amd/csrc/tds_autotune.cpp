@@ -290,7 +290,8 @@ int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* cons
     Events ev;
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
         return TDS_EHIP;
-    // the batch kernels share one register row bucket: 32 or 64 rows
+    // rows per block, 32 or 64 (the batch runs one launch of each kernel per
+    // register row bucket): first the same for every matrix
     const int32_t rows_c[2] = {32, 64};
     tds_handle hs[2] = {nullptr, nullptr};
     std::vector<int32_t> P(K);
@@ -299,38 +300,79 @@ int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* cons
         for (int32_t k = 0; k < K; ++k) P[k] = blocks_for(M[k], rows_c[c]);
         rc = tdsolve_batch_prepare(K, a, b, M, P.data(), &hs[c]);
     }
+    auto series = [&](tds_handle h) {
+        return tdsolve_batch_series(h, Fp.data(), Xp.data(), N, mode, stream);
+    };
     for (int round = 0; round < kRounds && !rc; ++round)
         for (int c = 0; c < 2 && !rc; ++c) {
             double ms = 0.0;
-            rc = time_calls(
-                [&] { return tdsolve_batch_series(hs[c], Fp.data(), Xp.data(), N, mode, stream); },
-                reps, s, ev, &ms);
+            rc = time_calls([&] { return series(hs[c]); }, reps, s, ev, &ms);
             best_ms[c] = std::min(best_ms[c], ms);
         }
-    const int pick = best_ms[1] < best_ms[0] ? 1 : 0;
+    const int uni = best_ms[1] < best_ms[0] ? 1 : 0;
+    tds_handle cur = hs[uni];
+    if (hs[1 - uni]) tdsolve_destroy(hs[1 - uni]);
+    hs[0] = hs[1] = nullptr;
+    double cur_ms = best_ms[uni];
+    std::vector<int32_t> rows(K, rows_c[uni]);
+    // then per matrix: the matrices in four classes of equal count by size
+    // (M[k] N[k]); from the uniform choice, each class's rows per block are
+    // flipped in turn, largest class first, and kept when the batch is
+    // faster (the current and the flipped batch timed in alternation)
+    std::vector<int32_t> order(K);
+    for (int32_t k = 0; k < K; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return (double)M[x] * (double)N[x] < (double)M[y] * (double)N[y];
+    });
+    const int32_t classes = K >= 4 ? 4 : 1;
+    for (int32_t c = classes - 1; c >= 0 && !rc; --c) {
+        const int32_t k0 = (int32_t)((int64_t)K * c / classes);
+        const int32_t k1 = (int32_t)((int64_t)K * (c + 1) / classes);
+        std::vector<int32_t> trial(rows);
+        for (int32_t i = k0; i < k1; ++i) trial[order[i]] = trial[order[i]] == 32 ? 64 : 32;
+        for (int32_t k = 0; k < K; ++k) P[k] = blocks_for(M[k], trial[k]);
+        tds_handle th = nullptr;
+        rc = tdsolve_batch_prepare(K, a, b, M, P.data(), &th);
+        double t_cur = INFINITY, t_try = INFINITY;
+        for (int round = 0; round < kRounds && !rc; ++round) {
+            double ms = 0.0;
+            rc = time_calls([&] { return series(cur); }, reps, s, ev, &ms);
+            t_cur = std::min(t_cur, ms);
+            if (!rc) rc = time_calls([&] { return series(th); }, reps, s, ev, &ms);
+            t_try = std::min(t_try, ms);
+        }
+        if (!rc && t_try < t_cur) {
+            tdsolve_destroy(cur);
+            cur = th;
+            rows = trial;
+            cur_ms = t_try;
+        } else {
+            if (th) tdsolve_destroy(th);
+            if (!rc) cur_ms = std::min(cur_ms, t_cur);
+        }
+    }
     // refinement passes: the fewest (1..3) whose largest normwise backward
     // error on these right-hand sides stays within kPassesSlack times that
     // of the same solve in FP64 arithmetic (TDS_F32_WIDE)
     int32_t passes = 0;
     if (!rc && mode == TDS_F32_REFINED) {
         double eta_wide = 0.0;
-        rc = tdsolve_batch_series(hs[pick], Fp.data(), Xp.data(), N, TDS_F32_WIDE, stream);
-        if (!rc) rc = tdsolve_status(hs[pick], stream, &eta_wide, nullptr);
+        rc = tdsolve_batch_series(cur, Fp.data(), Xp.data(), N, TDS_F32_WIDE, stream);
+        if (!rc) rc = tdsolve_status(cur, stream, &eta_wide, nullptr);
         for (passes = 1; !rc && passes <= 3; ++passes) {
             double eta = 0.0;
-            rc = tdsolve_set_refinement(hs[pick], passes);
-            if (!rc) rc = tdsolve_batch_series(hs[pick], Fp.data(), Xp.data(), N, mode, stream);
-            if (!rc) rc = tdsolve_status(hs[pick], stream, &eta, nullptr);
+            rc = tdsolve_set_refinement(cur, passes);
+            if (!rc) rc = series(cur);
+            if (!rc) rc = tdsolve_status(cur, stream, &eta, nullptr);
             if (!rc && eta <= kPassesSlack * eta_wide) break;
         }
         if (passes > 3) passes = 3;
     }
-    for (int c = 0; c < 2; ++c)
-        if (hs[c]) tdsolve_destroy(hs[c]);
+    if (cur) tdsolve_destroy(cur);
     if (rc) return rc;
-    for (int32_t k = 0; k < K; ++k) P_out[k] = blocks_for(M[k], rows_c[pick]);
+    for (int32_t k = 0; k < K; ++k) P_out[k] = blocks_for(M[k], rows[k]);
     if (passes_out) *passes_out = passes;
-    if (ms_out) *ms_out = best_ms[pick];
+    if (ms_out) *ms_out = cur_ms;
     return TDS_OK;
 }
 

@@ -193,18 +193,22 @@ struct BatchDesc {
     DevTables H;       // half-block tables (half_tables), when the batch uses them
 };
 
-// The three steps for all matrices of a batch: one launch each.  `bucket`
-// is the common register-sweep row bucket (32 or 64); `halves`: every
-// matrix's BatchDesc::H holds its half-block tables (bucket 64), and the
-// sweeps with FP64 results take the blocks in halves.
+// The three steps for all matrices of a batch.  The beta and sweep items of
+// the matrices whose blocks fit the 32-row register bucket come first
+// (items32 of them), then those of the 64-row bucket (items64; their
+// BatchDesc::item0 counts from the start of that group): one launch of each
+// kernel per non-empty group, one interface launch for all.  `halves`:
+// every 64-row matrix's BatchDesc::H holds its half-block tables, and the
+// sweeps with FP64 results take those blocks in halves.
 // `tm` (may be null): start/stop events of the beta, interface and sweep
-// launches, in that order (the interface pair stays unrecorded when no
+// phases, in that order (a phase of two launches starts with the first and
+// stops with the second; the interface pair stays unrecorded when no
 // matrix has interface rows, scans == 0).
 // own_items[i] / own_scans[i]: the matrix of beta-and-sweep item i / of
-// interface item i (device arrays of items / scans entries).
+// interface item i (device arrays of items32 + items64 / scans entries).
 hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items,
-                        const int32_t* own_scans, int64_t items, int64_t scans,
-                        int32_t bucket, int mode, int passes, bool halves,
+                        const int32_t* own_scans, int64_t items32, int64_t items64,
+                        int64_t scans, int mode, int passes, bool halves,
                         const KTime* tm, hipStream_t s);
 
 // uniform[-1, 1) values from a counter-based generator (timing inputs)

@@ -1832,36 +1832,54 @@ static void batch_sweep(const BatchDesc* D, const int32_t* own, int64_t items, i
 }
 
 hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items, const int32_t* own_scans,
-                        int64_t items, int64_t scans, int32_t bucket, int mode, int passes,
+                        int64_t items32, int64_t items64, int64_t scans, int mode, int passes,
                         bool halves, const KTime* tm, hipStream_t s) {
-    if (items == 0) return hipSuccess;
-    if (bucket != 32 && bucket != 64) return hipErrorInvalidValue;
-    if (items > INT32_MAX) return hipErrorInvalidValue;
-    const dim3 g((unsigned)items);
+    if (items32 + items64 == 0) return hipSuccess;
+    if (items32 > INT32_MAX || items64 > INT32_MAX || scans > INT32_MAX)
+        return hipErrorInvalidValue;
     const bool f64in = (mode == TDS_F64);
-    if (bucket == 32) {
+    const int32_t* own64 = own_items + items32;
+    // a phase of two launches: its start event on the first, its stop on
+    // the second
+    KTime t1[3], t2[3];
+    const KTime* p1[3] = {nullptr, nullptr, nullptr};
+    const KTime* p2[3] = {nullptr, nullptr, nullptr};
+    if (tm) {
+        for (int q = 0; q < 3; ++q) {
+            if (items32 > 0 && items64 > 0 && q != 1) {
+                t1[q] = KTime{tm[q].start, nullptr};
+                t2[q] = KTime{nullptr, tm[q].stop};
+                p1[q] = &t1[q];
+                p2[q] = &t2[q];
+            } else {
+                p1[q] = p2[q] = &tm[q];
+            }
+        }
+    }
+    if (items32 > 0) {
+        const dim3 g((unsigned)items32);
         if (f64in)
-            launch_k(k_beta_batch<32, double>, g, dim3(kWG), 0, s, tm, D, own_items);
+            launch_k(k_beta_batch<32, double>, g, dim3(kWG), 0, s, p1[0], D, own_items);
         else
-            launch_k(k_beta_batch<32, float>, g, dim3(kWG), 0, s, tm, D, own_items);
-    } else {
+            launch_k(k_beta_batch<32, float>, g, dim3(kWG), 0, s, p1[0], D, own_items);
+    }
+    if (items64 > 0) {
+        const dim3 g((unsigned)items64);
         if (f64in)
-            launch_k(k_beta_batch<64, double>, g, dim3(kWG), 0, s, tm, D, own_items);
+            launch_k(k_beta_batch<64, double>, g, dim3(kWG), 0, s, p2[0], D, own64);
         else
-            launch_k(k_beta_batch<64, float>, g, dim3(kWG), 0, s, tm, D, own_items);
+            launch_k(k_beta_batch<64, float>, g, dim3(kWG), 0, s, p2[0], D, own64);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (scans > 0) {
-        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanBatchThreads), 0, s,
-                 tm ? tm + 1 : nullptr, D, own_scans);
+        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanBatchThreads), 0, s, p1[1], D,
+                 own_scans);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (bucket == 32)
-        batch_sweep<32>(D, own_items, items, mode, passes, false, s, tm ? tm + 2 : nullptr);
-    else
-        batch_sweep<64>(D, own_items, items, mode, passes, halves, s, tm ? tm + 2 : nullptr);
+    if (items32 > 0) batch_sweep<32>(D, own_items, items32, mode, passes, false, s, p1[2]);
+    if (items64 > 0) batch_sweep<64>(D, own64, items64, mode, passes, halves, s, p2[2]);
     return hipGetLastError();
 }
 

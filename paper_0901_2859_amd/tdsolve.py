@@ -549,12 +549,12 @@ def autotune(a, b, N: int, mode="f32_refined", reps: int = 5, cache: bool = True
 
 def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
                    cache: bool = True, stream=None, with_passes: bool = False):
-    """Block counts for an uneven batch (tdsolve_batch_autotune: one shared
-    choice of 32 or 64 rows per block, timed on the whole batch, and the
-    refinement passes of the refined mode chosen by accuracy).  Cached like
-    autotune(), by device, mode and the digest of the (M, N) list.  Returns
-    (list of P, ms per batch solve), or (list of P, passes, ms) with
-    with_passes."""
+    """Block counts for an uneven batch (tdsolve_batch_autotune: 32 or 64
+    rows per block for every matrix, then per class of matrices by size,
+    timed on the whole batch, and the refinement passes of the refined mode
+    chosen by accuracy).  Cached like autotune(), by device, mode and the
+    digest of the (M, N) list.  Returns (list of P, ms per batch solve), or
+    (list of P, passes, ms) with with_passes."""
     m = mode_id(mode)
     K = len(b_list)
     bs = [_host_f64(b) for b in b_list]
@@ -562,7 +562,7 @@ def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
     Ms = np.array([x.shape[0] for x in bs], dtype=np.int64)
     Ns = np.array([int(n) for n in N_list], dtype=np.int64)
     digest = hashlib.sha256(Ms.tobytes() + Ns.tobytes()).hexdigest()[:16]
-    key = f"batch|{_device_key()}|K={K}|MN={digest}|mode={m}"
+    key = f"batch-per-matrix|{_device_key()}|K={K}|MN={digest}|mode={m}"
     hit = _cache_load().get(key) if cache else None
     if hit is not None and "passes" in hit:
         Pl, passes, ms = [int(p) for p in hit["P"]], int(hit["passes"]), float(hit["ms"])

@@ -140,5 +140,9 @@ def test_batch_autotune_passes(tmp_path, monkeypatch):
     Ns = [it["N"] for it in items]
     P_l, passes, ms = t.batch_autotune(a_l, b_l, Ns, "f32_refined", with_passes=True)
     assert 1 <= passes <= 3 and ms > 0
+    # per matrix, 32 or 64 rows per block
+    for it, P in zip(items, P_l):
+        M = it["M"]
+        assert P in (max(1, min(-(-M // 32), M // 2)), max(1, min(-(-M // 64), M // 2))), (M, P)
     assert t.batch_autotune(a_l, b_l, Ns, "f32_refined", with_passes=True) == (P_l, passes, ms)
     assert t.batch_autotune(a_l, b_l, Ns, "f64", with_passes=True)[1] == 0

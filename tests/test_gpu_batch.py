@@ -82,6 +82,28 @@ def test_batch_matches_single_plans_bitwise(mode):
         assert torch.equal(X1, Xs[k])
 
 
+@pytest.mark.parametrize("mode", ["f32_refined", "f64", "f32_wide"])
+def test_batch_mixed_row_buckets_bitwise(mode):
+    # per-matrix block counts: 32-row blocks for some matrices, 64-row blocks
+    # (swept in halves) for the others, one launch of each kernel per bucket;
+    # every matrix bitwise its single plan, and the parity gates
+    w = wl.uneven_batch(seed=13, K=8, M_lo=300, M_hi=2500, N_hi=600)
+    items = w["items"]
+    P_l = [-(-it["M"] // (32 if k % 2 else 64)) for k, it in enumerate(items)]
+    rows = [-(-it["M"] // p) for it, p in zip(items, P_l)]
+    assert any(r <= 32 for r in rows) and any(35 <= r <= 64 for r in rows)
+    print(f"mixed buckets rows={rows} mode={mode}", flush=True)
+    bp = t.BatchPlan([it["a"] for it in items], [it["b"] for it in items], P_l)
+    Fs = [torch.from_numpy(it["F"]).to(DEV) for it in items]
+    if mode == "f64":
+        Fs = [F.double() for F in Fs]
+    Xs = bp.solve(Fs, mode=mode)
+    for k, it in enumerate(items):
+        X1 = t.Plan(it["a"], it["b"], P_l[k]).solve(Fs[k], mode=mode)
+        assert torch.equal(X1, Xs[k]), f"matrix {k} ({rows[k]} rows per block)"
+        _check(it["a"], it["b"], it["F"].astype(np.float64), Xs[k].cpu().numpy(), P_l[k])
+
+
 def test_batch_graph_replays():
     # capture the batch solve once, replay it several times with eager work
     # and synchronizations in between; every replay must equal the eager solve
