@@ -762,9 +762,9 @@ __device__ __forceinline__ void refined_solve(const DevTables& T, int64_t i0,
 // block) of cnt rows whose boundary values are known: xL beside its first
 // row (coupling cl) and xR beside row cnt-1 (coupling cr); x holds the
 // block's values including the boundary responses.  The residual is formed
-// in FP64 with the boundary terms, eliminated in FP32 as in the other
-// passes, and the back substitution carries each row's rounded update into
-// the next row in FP64:
+// in FP64 with the boundary terms and eliminated in FP32 as in the other
+// passes (boundary_elim), and the back substitution carries each row's
+// rounded update into the next row in FP64 (carried_back_sub):
 //     y_r = x_r + (w_r - cp_r (y_{r+1} - x_{r+1})),
 // so the result is the solution of the bidiagonal system U y = U x + w up
 // to one rounding per row, as in a direct sweep: its rounding errors stay
@@ -772,10 +772,10 @@ __device__ __forceinline__ void refined_solve(const DevTables& T, int64_t i0,
 // every row (which would raise the residual by about the ratio of |A| to
 // the elimination's lower factor).
 template <int TMAX, bool GEN, int STRIDE = kWG>
-__device__ __forceinline__ void refined_boundary_pass(const DevTables& T, int64_t i0,
-                                                      const float* __restrict__ my_f, int cnt,
-                                                      double cl, double xL, double cr, double xR,
-                                                      double (&x)[TMAX]) {
+__device__ __forceinline__ void boundary_elim(const DevTables& T, int64_t i0,
+                                              const float* __restrict__ my_f, int cnt, double cl,
+                                              double xL, double cr, double xR,
+                                              const double (&x)[TMAX], float (&w)[TMAX]) {
     asm volatile("" ::: "memory");
     int z;
     asm volatile("s_mov_b32 %0, 0" : "=s"(z));
@@ -783,8 +783,7 @@ __device__ __forceinline__ void refined_boundary_pass(const DevTables& T, int64_
     const cptr<double> inl64p = GEN ? cst(T.inl64 + i0) + z : in64p;
     const cptr<double> b64p = cst(T.b64 + i0) + z;
     const cptr<float> inl32p = cst((GEN ? T.inl32 : T.in32) + i0) + z;
-    const cptr<float> cp32p = cst(T.cp32 + i0) + z, rd32p = cst(T.rd32 + i0) + z;
-    float w[TMAX];
+    const cptr<float> rd32p = cst(T.rd32 + i0) + z;
 #pragma unroll
     for (int r = 0; r < TMAX; ++r) {
         if ((r & 3) == 0) __builtin_amdgcn_sched_barrier(0);
@@ -797,7 +796,18 @@ __device__ __forceinline__ void refined_boundary_pass(const DevTables& T, int64_
         const float sub = (r > 0) ? inl32p[r - 1] : 0.0f;
         w[r] = ((float)res - sub * prev) * rd32p[r];
     }
-    double carry = 0.0;
+}
+
+// carry: the update beyond the last row (zero, or a correction of the value
+// there, entering the last row through coupling c_last)
+template <int TMAX>
+__device__ __forceinline__ void carried_back_sub(const DevTables& T, int64_t i0,
+                                                 const float (&w)[TMAX], double carry,
+                                                 double c_last, double (&x)[TMAX]) {
+    asm volatile("" ::: "memory");
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    const cptr<float> cp32p = cst(T.cp32 + i0) + z;
 #pragma unroll
     for (int r = TMAX - 1; r >= 0; --r) {
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -805,10 +815,21 @@ __device__ __forceinline__ void refined_boundary_pass(const DevTables& T, int64_
         // every row's w in FP64)
         float wr = w[r];
         asm volatile("" : "+v"(wr));
-        const double y = x[r] + fma(-(double)cp32p[r], carry, (double)wr);
+        const double cp = (r == TMAX - 1) ? c_last : (double)cp32p[r];
+        const double y = x[r] + fma(-cp, carry, (double)wr);
         carry = y - x[r];
         x[r] = y;
     }
+}
+
+template <int TMAX, bool GEN, int STRIDE = kWG>
+__device__ __forceinline__ void refined_boundary_pass(const DevTables& T, int64_t i0,
+                                                      const float* __restrict__ my_f, int cnt,
+                                                      double cl, double xL, double cr, double xR,
+                                                      double (&x)[TMAX]) {
+    float w[TMAX];
+    boundary_elim<TMAX, GEN, STRIDE>(T, i0, my_f, cnt, cl, xL, cr, xR, x, w);
+    carried_back_sub<TMAX>(T, i0, w, 0.0, 0.0, x);
 }
 
 template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
@@ -1043,7 +1064,8 @@ constexpr uint32_t kXcdsSweep = 8;   // XCDs of the chip (workgroups dispatched 
 // blocks) x RHS right-hand sides from tile * RHS, on 2 RHS threads.  KIND:
 // kSweepRefined (FP32 input, refined_solve; s_f: kHalfRows x 2 RHS floats of
 // LDS) or kSweep64 (FP64 arithmetic on FP32 or FP64 input, no refinement;
-// s_f unused).  s_q: 2 RHS doubles of LDS.
+// s_f unused).  s_q: 2 RHS doubles of LDS (refined: 4 RHS, the second
+// half for the last pass's exchange).
 // The item's two interface values are read before its loads of F, or, with
 // a Wait functor whose kFused is true (the fused order), only after the
 // zero-boundary solves and a call of wait(), which returns once the
@@ -1061,6 +1083,7 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
                                             int64_t tile, const double* __restrict__ xsep,
                                             int passes, float* s_f, double* s_q,
                                             Wait wait = Wait()) {
+    double* s_q2 = s_q + 2 * RHS;    // refined: the second exchange
     constexpr int TM = kHalfRows, NT = 2 * RHS;
     const int32_t P = H.P >> 1;                 // blocks of the method's partition
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / RHS);   // 0 left, 1 right
@@ -1148,24 +1171,61 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
     }
     __syncthreads();
     const int64_t m = cst(H.starts)[2 * j + 1];
-    const double xm = (s_q[c] - cst(H.a64)[m] * s_q[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
-    if (!live) return;
+    double xm = (s_q[c] - cst(H.a64)[m] * s_q[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
     double* xb = X + i0 * N + n0;
     if constexpr (KIND == kSweepRefined) {
-        // superposition, then (one or more passes) a pass over the half
-        // with its boundary values x(s_j), x_m or x_m, x(s_{j+1})
+        // superposition, then (one or more passes) the last pass over the
+        // block with its boundary values: each half's residual with x(s_j),
+        // x_m or x_m, x(s_{j+1}) eliminated in FP32; row m's correction
+        //     dm = (r_m - A[m][m-1] dA_{m-1} - A[m][m+1] dB_{m+1}) mid_inv
+        // from the halves' FP32 corrections next to m (one LDS exchange);
+        // then each half's back substitution with dm at m, carrying each
+        // row's rounded update (carried_back_sub)
         const double xl = h ? xm : xo, xr = h ? xo : xm;
 #pragma unroll
         for (int r = 0; r < TM; ++r) x[r] = fma(xr, vv[r], fma(xl, uu[r], x[r]));
         if (passes >= 1) {
+            const double a_l = cst(GEN ? H.l64 : H.a64)[m - 1];    // A[m][m-1]
+            const double a_r = cst(H.a64)[m];                       // A[m][m+1]
             const double cl = (h == 0 && j == 0) ? 0.0 : cst(GEN ? H.l64 : H.a64)[i0 - 1];
             const double cr = cst(H.a64)[seg_hi - 1];      // zero past the last row
-            refined_boundary_pass<TM, GEN, NT>(H, i0, s_f + threadIdx.x, cnt, cl, xl, cr, xr, x);
+            float w[TM];
+            boundary_elim<TM, GEN, NT>(H, i0, s_f + threadIdx.x, cnt, cl, xl, cr, xr, x, w);
+            const cptr<float> cp32 = cst(H.cp32 + i0), rd32 = cst(H.rd32 + i0);
+            if (h == 0) {
+                // the left half's last eliminated value is its correction
+                // there (its last elimination factor is zero)
+                s_q2[c] = fm - a_l * x[TM - 1] - cst(H.b64)[m] * xm - a_l * (double)w[TM - 1];
+            } else {
+                float d = 0.0f;
+#pragma unroll
+                for (int r = TM - 1; r >= 0; --r) d = w[r] - cp32[r] * d;
+                s_q2[RHS + c] = x[0] + (double)d;
+            }
+            __syncthreads();
+            const double dm = (s_q2[c] - a_r * s_q2[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
+            if (h == 1) {
+                // dm enters the right half's first row: the eliminated
+                // response to it, row by row
+                const cptr<float> inl32 = cst((GEN ? H.inl32 : H.in32) + i0);
+                const float dmf = (float)dm;
+                float e = -(float)cst(GEN ? H.l64 : H.a64)[m] * rd32[0];
+#pragma unroll
+                for (int r = 0; r < TM; ++r) {
+                    if (r > 0) e = -inl32[r - 1] * e * rd32[r];
+                    w[r] = fmaf(dmf, e, w[r]);
+                }
+            }
+            carried_back_sub<TM>(H, i0, w, h == 0 ? dm : 0.0,
+                                 h == 0 ? cst(H.a64)[m - 1] * (double)rd32[TM - 1] : 0.0, x);
+            xm += dm;
         }
+        if (!live) return;
 #pragma unroll
         for (int r = 0; r < TM; ++r)
             if (r < cnt) store_x(&(xb + (int64_t)r * N)[c], x[r]);
     } else {
+        if (!live) return;
         // back substitution outward from m, slots TM-1 .. 0
         const cptr<double> tc = cst(H.tw_c + sb);
         double y = xm;
@@ -1189,7 +1249,7 @@ __global__ __launch_bounds__(2 * RHS, 4) void k_sweep_halves(DevTables H,
                                                              const double* __restrict__ xsep,
                                                              int passes) {
     __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * RHS : 1];
-    __shared__ double s_q[2 * RHS];
+    __shared__ double s_q[(KIND == kSweepRefined ? 4 : 2) * RHS];
     // Order of the work: the blocks in reverse, so the rows the beta pass
     // read last are swept first, and each tile on the XCD that read its
     // columns in the beta pass (workgroup w runs on XCD w % 8; k_beta_vec's
@@ -1311,10 +1371,10 @@ struct FuseWait {
 };
 
 // LDS of a fused workgroup (doubles): the largest of the halves sweep
-// (refined: kHalfRows x 2 kHalfRhs floats of F, then 2 kHalfRhs doubles;
-// FP64 arithmetic: the 2 kHalfRhs doubles only), the beta reduction and the
+// (refined: kHalfRows x 2 kHalfRhs floats of F, then 4 kHalfRhs doubles;
+// FP64 arithmetic: 2 kHalfRhs doubles), the beta reduction and the
 // 256-thread interface scan
-constexpr int kFuseSweepLds = kHalfRows * kHalfRhs + 2 * kHalfRhs;
+constexpr int kFuseSweepLds = kHalfRows * kHalfRhs + 4 * kHalfRhs;
 constexpr int kFuseSweep64Lds = 2 * kHalfRhs;
 constexpr int kFuseScanLds = 2 * kScanBatchThreads + 2 * kScanMaxGroupsSingle +
                              kScanBatchThreads * kScanMaxPer;
@@ -1497,7 +1557,7 @@ __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDe
                                                                    const int32_t* __restrict__ own,
                                                                    int passes) {
     __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * kWG : 1];
-    __shared__ double s_q[2 * kWG];
+    __shared__ double s_q[(KIND == kSweepRefined ? 4 : 2) * kWG];
     const int64_t item = xcd_item();
     const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
