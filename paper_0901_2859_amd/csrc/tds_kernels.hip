@@ -791,7 +791,9 @@ __device__ __forceinline__ void boundary_elim(const DevTables& T, int64_t i0,
         if (r > 0) res -= inl64p[r - 1] * x[r - 1];
         if (r + 1 < TMAX) res -= in64p[r] * x[r + 1];
         if (r == 0) res -= cl * xL;
-        if (r == cnt - 1) res -= cr * xR;
+        // the right boundary's row: a scalar select of the coupling, not a
+        // per-lane select of the residual
+        res = fma(-((r == cnt - 1) ? cr : 0.0), xR, res);
         const float prev = (r > 0) ? w[r - 1] : 0.0f;
         const float sub = (r > 0) ? inl32p[r - 1] : 0.0f;
         w[r] = ((float)res - sub * prev) * rd32p[r];
@@ -1191,7 +1193,13 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
             const double cr = cst(H.a64)[seg_hi - 1];      // zero past the last row
             float w[TM];
             boundary_elim<TM, GEN, NT>(H, i0, s_f + threadIdx.x, cnt, cl, xl, cr, xr, x, w);
-            const cptr<float> cp32 = cst(H.cp32 + i0), rd32 = cst(H.rd32 + i0);
+            // tables read again here through an offset the compiler cannot
+            // see through: kept from the first sweeps, their values would
+            // hold some 64 scalar registers across the kernel (spilled)
+            asm volatile("" ::: "memory");
+            int z;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+            const cptr<float> cp32 = cst(H.cp32 + i0) + z, rd32 = cst(H.rd32 + i0) + z;
             if (h == 0) {
                 // the left half's last eliminated value is its correction
                 // there (its last elimination factor is zero)
@@ -1207,7 +1215,7 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
             if (h == 1) {
                 // dm enters the right half's first row: the eliminated
                 // response to it, row by row
-                const cptr<float> inl32 = cst((GEN ? H.inl32 : H.in32) + i0);
+                const cptr<float> inl32 = cst((GEN ? H.inl32 : H.in32) + i0) + z;
                 const float dmf = (float)dm;
                 float e = -(float)cst(GEN ? H.l64 : H.a64)[m] * rd32[0];
 #pragma unroll
