@@ -14,7 +14,8 @@ namespace tds {
 constexpr int kWG = 256;
 constexpr int kScanRhs = 16;      // right-hand sides per scan group (single-matrix kernel)
 constexpr int kScanRhsLog2 = 4;
-constexpr int kScanBatchThreads = 256;   // batch scan workgroup: G groups x R RHS
+constexpr int kScanBatchThreads = 256;   // fused order's scan workgroup: G groups x R RHS
+constexpr int kScanBatchWide = 512;      // batch scan workgroup: G groups x R RHS
 constexpr int kScanBatchMaxGroups = 32;  // groups per batch scan workgroup, at most
 
 // Largest block (rows of one segment) handled by the register-resident
@@ -168,7 +169,7 @@ int32_t rows_bucket(int32_t max_rows);
 // (<= max_groups; 16 for the batch kernels)
 void scan_shape(int32_t P, int32_t max_groups, int32_t* per, int32_t* G);
 // the batch kernel's shape for one matrix: per, G and log2 R with
-// G R <= kScanBatchThreads
+// G R <= kScanBatchWide
 void batch_scan_shape(int32_t P, int32_t* per, int32_t* G, int32_t* lgR);
 
 // One matrix of a batch: its tables, its series and its slices of the work

@@ -1526,14 +1526,14 @@ __global__ __launch_bounds__(kWG) void k_beta_batch(const BatchDesc* __restrict_
                               (local % tiles) * kWG + wv * kBetaRhs, d.betaR, d.betaL);
 }
 
-// one workgroup of kScanBatchThreads per R_k right-hand sides of matrix k
-// (G_k R_k <= kScanBatchThreads); LDS for the largest shape, G R = 256 with
-// per <= kScanMaxPer
-__global__ __launch_bounds__(kScanBatchThreads) void k_iface_batch(
+// one workgroup of kScanBatchWide per R_k right-hand sides of matrix k
+// (G_k R_k <= kScanBatchWide); LDS for the largest shape, G R =
+// kScanBatchWide with per <= kScanMaxPer
+__global__ __launch_bounds__(kScanBatchWide) void k_iface_batch(
     const BatchDesc* __restrict__ D, const int32_t* __restrict__ own) {
     // carries 2 G R + factors 2 G + S^R by row G per R, with G R <= 256
-    __shared__ double S[2 * kScanBatchThreads + 2 * kScanMaxGroupsSingle +
-                        kScanBatchThreads * kScanMaxPer];
+    __shared__ double S[2 * kScanBatchWide + 2 * kScanMaxGroupsSingle +
+                        kScanBatchWide * kScanMaxPer];
     const int64_t item = xcd_item();
     const int32_t k = cst(own)[item];
     const BatchDesc d = D[k];    // uniform, before any store: scalar loads
@@ -1644,12 +1644,12 @@ void batch_scan_shape(int32_t P, int32_t* per, int32_t* G, int32_t* lgR) {
     // the groups of the single-matrix scan (scan_shape: at least 4 blocks
     // per group, at most kScanMaxGroupsSingle groups), so that a matrix's
     // interface values are bitwise those of its single plan, on a workgroup
-    // of kScanBatchThreads: G groups x R = 2^lgR right-hand sides, R the
-    // largest power of two with G R <= kScanBatchThreads.  Small systems get
+    // of kScanBatchWide: G groups x R = 2^lgR right-hand sides, R the
+    // largest power of two with G R <= kScanBatchWide.  Small systems get
     // many right-hand sides per workgroup, large ones many short groups.
     scan_shape(P, kScanMaxGroupsSingle, per, G);
     int32_t lg = 0;
-    while ((1 << (lg + 1)) * *G <= kScanBatchThreads) ++lg;
+    while ((1 << (lg + 1)) * *G <= kScanBatchWide) ++lg;
     *lgR = lg;
 }
 
@@ -1941,7 +1941,7 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items, const int3
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (scans > 0) {
-        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanBatchThreads), 0, s, p1[1], D,
+        launch_k(k_iface_batch, dim3((unsigned)scans), dim3(kScanBatchWide), 0, s, p1[1], D,
                  own_scans);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
