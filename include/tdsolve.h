@@ -249,8 +249,8 @@ int tdsolve_set_interface(tds_handle h, int32_t order);
  * soon after the weights did.  Same work items and arithmetic as the three
  * launches: bitwise the same X.  Taken when the plan sweeps its blocks in
  * halves (tdsolve_info.sweep_halves), the mode has FP64 results, the order
- * is the recurrence or the dense one, N is a multiple of 4 (FP32 input) or
- * 2 (FP64 input) and F is 16-byte aligned; otherwise the three launches
+ * is the recurrence or the dense one, N is even and F is 8-byte (FP32
+ * input) or 16-byte (FP64 input) aligned; otherwise the three launches
  * run.  Phase timing then reports the fused kernel as the sweep phase.
  * Errors: TDS_EINVAL (batch handle, lag outside 0..64, a bad tile). */
 int tdsolve_set_fused(tds_handle h, int32_t lag, int32_t tile);

@@ -150,8 +150,8 @@ hipError_t launch_sweep(const DevTables& t, const void* F, void* X, int64_t N,
 // one launch over tiles of W right-hand sides (a multiple of 256), the
 // sweeps of a tile `lag` stages (tiles) after its weights (lag >= 1).  Needs the half-block tables
 // h (blocks of 33..64 rows), FP64 results, the recurrence order (Kt null) or
-// the dense one (Kt, Pc, Mr as for launch_iface_dense), N a multiple of 4
-// (FP32 input) or 2 (FP64) and F 16-byte aligned (fused_fits); sync: device
+// the dense one (Kt, Pc, Mr as for launch_iface_dense), N even and F 8-byte
+// (FP32 input) or 16-byte (FP64) aligned (fused_fits); sync: device
 // ints, fused_sync_ints(N) of them, zeroed by the launcher.  `tm` times the
 // fused kernel.
 bool fused_fits(const DevTables& t, const DevTables* halves, const void* F, int64_t N, int mode,

@@ -13,8 +13,8 @@
 // when their pointers come from a descriptor table, as in the batch.)
 //
 //   beta   eq. beta_symn: beta^R_j, beta^L_j of block j (FP64 accumulation;
-//          rows of whole 16-byte groups are read four (FP32) or two (FP64)
-//          right-hand sides per lane).
+//          rows are read two right-hand sides per lane, 8- or 16-byte
+//          loads).
 //   iface  Theorem 2 (eq. theor_2): x at the interface rows, in one of three
 //          orders: the two first-order recurrences S^R_{k+1} = rho_k S^R_k +
 //          beta^R_k and S^L_k = beta^L_k + lam_k S^L_{k+1}, x(s_k) = S^R_k +
@@ -177,19 +177,21 @@ __device__ __forceinline__ void beta_item(const DevTables& T, const Fin* __restr
     }
 }
 
-// beta_item with V right-hand sides per lane read by one 16-byte load per
-// row (FP32 input: V = 4; FP64 input: V = 2), N a multiple of V and F
-// 16-byte aligned: each row access of a wavefront is one 1 KB span, a V-th
-// of the load instructions.  Per right-hand side the arithmetic is
-// beta_item's (the same rows per wavefront in the same order, the same
-// reduction), so the weights are bitwise the same.  Item (tile, j): block j
-// x 64 V right-hand sides.
+// beta_item with V = 2 right-hand sides per lane read by one load per row
+// (8 bytes on FP32 input, 16 on FP64), N a multiple of 2 and F aligned to
+// the load: half the load instructions, and tiles of 128 right-hand sides,
+// the halves sweep's own tiles.  Four right-hand sides per lane (16-byte
+// loads, 256-RHS tiles) on FP32 input made the ADI lines' beta pass 54 us
+// against 50 us: twice the work per workgroup over half the workgroups.
+// Per right-hand side the arithmetic is beta_item's (the same rows per
+// wavefront in the same order, the same reduction), so the weights are
+// bitwise the same.  Item (tile, j): block j x 64 V right-hand sides.
 template <typename Fin>
-struct Vec16;                  // 16 bytes of Fin
+struct Vec16;                  // the load of V right-hand sides of Fin
 template <>
 struct Vec16<float> {
-    static constexpr int V = 4;
-    using type = float4;
+    static constexpr int V = 2;
+    using type = float2;
 };
 template <>
 struct Vec16<double> {
@@ -1023,8 +1025,7 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
     // the FP32 elimination values
     __shared__ float s_f[KIND == kSweepRefined ? TMAX * kWG : 1];
     // FP32 input: the blocks in reverse, so the rows the beta pass read last
-    // are swept first (k_beta_vec's FP32 tiles are this kernel's 256 RHS, so
-    // each tile already runs on the XCD that read it; see k_sweep_halves)
+    // are swept first (see k_sweep_halves)
     const int32_t j = std::is_same<Fin, float>::value ? (int32_t)(gridDim.y - 1 - blockIdx.y)
                                                       : (int32_t)blockIdx.y;
     sweep_item<TMAX, Fin, Xout, KIND, GEN>(T, F, X, N, j, (int64_t)blockIdx.x, xsep, passes, s_f);
@@ -1259,23 +1260,15 @@ __global__ __launch_bounds__(2 * RHS, 4) void k_sweep_halves(DevTables H,
     __shared__ float s_f[KIND == kSweepRefined ? kHalfRows * 2 * RHS : 1];
     __shared__ double s_q[(KIND == kSweepRefined ? 4 : 2) * RHS];
     // Order of the work: the blocks in reverse, so the rows the beta pass
-    // read last are swept first, and each tile on the XCD that read its
-    // columns in the beta pass (workgroup w runs on XCD w % 8; k_beta_vec's
-    // tiles are 256 RHS on FP32 input, two tiles of this kernel, remapped
-    // when the tile count is a multiple of 2 kXcdsSweep, and 128 RHS on FP64
-    // input, the same tiles).  Poisson 4096 x 4096 on FP32 input: sweep
-    // 35.3-36.7 us in the plain order, 33.8 us reversed, 32.1-33.0 us with
-    // both; the bytes fetched past L2 stay the same, so the gain is in how
-    // fast those fetches are served.
-    uint32_t b = blockIdx.x;
+    // read last are swept first; k_beta_vec's tiles are this kernel's 128
+    // RHS, so tile b runs on the XCD (b % 8) that read its columns in the
+    // beta pass.  Poisson 4096 x 4096 on FP32 input: sweep 35.3-36.7 us in
+    // the plain order, 33.8 us reversed, 32.1-33.0 us reversed and on the
+    // beta pass's XCDs; the bytes fetched past L2 stay the same, so the gain
+    // is in how fast those fetches are served.
     const int32_t j = (int32_t)(gridDim.y - 1 - blockIdx.y);
-    if constexpr (std::is_same<Fin, float>::value) {
-        if (gridDim.x % (2 * kXcdsSweep) == 0) {
-            const uint32_t q = b % kXcdsSweep, r = b / kXcdsSweep;
-            b = 2 * (q + kXcdsSweep * (r / 2)) + (r % 2);
-        }
-    }
-    halves_item<RHS, Fin, KIND, GEN>(H, F, X, N, j, (int64_t)b, xsep, passes, s_f, s_q);
+    halves_item<RHS, Fin, KIND, GEN>(H, F, X, N, j, (int64_t)blockIdx.x, xsep, passes, s_f,
+                                     s_q);
 }
 
 template <typename Fin, typename Xout, int KIND, bool GEN>
@@ -1601,10 +1594,10 @@ int32_t rows_bucket(int32_t max_rows) {
 hipError_t launch_beta(const DevTables& t, const void* F, bool f32, int64_t N, double* betaR,
                        double* betaL, hipStream_t s, const KTime* tm) {
     if (t.P < 2 || N == 0) return hipSuccess;
-    // rows of whole 16-byte groups: four (FP32) or two (FP64) right-hand
-    // sides per lane
-    const int V = f32 ? 4 : 2;
-    if (N % V == 0 && ((uintptr_t)F & 15) == 0 &&
+    // two right-hand sides per lane, loads of 8 (FP32) or 16 (FP64) bytes
+    const int V = 2;
+    const uintptr_t align = f32 ? 7 : 15;
+    if (N % V == 0 && ((uintptr_t)F & align) == 0 &&
         (t.wpad_rows == 32 || t.wpad_rows == 64 || t.wpad_rows == 128)) {
         const dim3 gv((unsigned)((N + V * kBetaRhs - 1) / (V * kBetaRhs)), (unsigned)t.P, 1);
 #define TDS_BETA_VEC(TM, FT) \
@@ -1765,8 +1758,7 @@ bool fused_fits(const DevTables& t, const DevTables* halves, const void* F, int6
     if (mode == TDS_F32 || order == TDS_IFACE_DICHOTOMY || t.P < 2 || N == 0) return false;
     if (!halves || halves->P != 2 * t.P || t.wpad_rows != 64) return false;
     if (t.max_rows <= kHalfRows || t.max_rows > 2 * kHalfRows) return false;
-    const int V = mode == TDS_F64 ? 2 : 4;
-    return N % V == 0 && ((uintptr_t)F & 15) == 0;
+    return N % 2 == 0 && ((uintptr_t)F & (mode == TDS_F64 ? 15 : 7)) == 0;
 }
 
 int64_t fused_sync_ints(int64_t N) {
@@ -1779,7 +1771,7 @@ static hipError_t fused_t(const DevTables& t, const DevTables& h, const void* F,
                           int64_t N, int passes, double* betaR, double* betaL, double* xsep,
                           const double* Kt, int32_t Pc, int32_t Mr, int32_t lag, int32_t W,
                           int* sync, hipStream_t s, const KTime* tm) {
-    constexpr int32_t V = std::is_same<Fin, float>::value ? 4 : 2;
+    constexpr int32_t V = Vec16<Fin>::V;       // right-hand sides per lane of a beta item
     FuseShape fs;
     fs.W = W;
     fs.T = (N + W - 1) / W;

@@ -120,7 +120,8 @@ def test_refined_halves_reproducible_and_in_place_of_rows():
 @pytest.mark.parametrize("mode", ["f32_refined", "f64", "f32_wide"])
 def test_unaligned_series_takes_the_scalar_beta_path_bitwise(mode):
     # F starting one element past a 16-byte boundary cannot be read by the
-    # 16-byte-load beta kernel; the one-RHS-per-lane kernel forms the same
+    # vector-load beta kernel (8-byte loads on FP32 input, 16-byte on
+    # FP64); the one-RHS-per-lane kernel forms the same
     # weights in the same order, so X is bitwise that of the aligned solve
     rng = np.random.default_rng(17)
     M, N, P = 4096, 512, 64

@@ -231,10 +231,10 @@ def test_changing_n_and_graph_replays():
 @pytest.mark.parametrize("M,N,P,offset", [
     # blocks of 62-64 rows: the refined sweep's pipelined kernel, whose
     # wavefronts walk several tiles of 64 right-hand sides each
-    (2000, 4099, 32, 0),    # N % 4 != 0: 4-byte row loads, ragged last tile
-    (2000, 4100, 32, 0),    # 16-byte row loads except in the ragged last tile
+    (2000, 4099, 32, 0),    # odd N: 4-byte row loads, ragged last tile
+    (2000, 4100, 32, 0),    # 8-byte row loads except in the ragged last tile
     (4096, 2048, 64, 0),    # full tiles, two per wavefront
-    (1000, 1024, 16, 1),    # F 4 bytes past a 16-byte boundary: 4-byte loads
+    (1000, 1024, 16, 1),    # F 4 bytes past an 8-byte boundary: 4-byte loads
 ])
 def test_refined_many_tiles_per_wavefront(M, N, P, offset):
     print(f"case M={M} N={N} P={P} offset={offset}", flush=True)
