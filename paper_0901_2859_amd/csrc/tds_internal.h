@@ -16,7 +16,6 @@ constexpr int kScanRhs = 16;      // right-hand sides per scan group (single-mat
 constexpr int kScanRhsLog2 = 4;
 constexpr int kScanBatchThreads = 256;   // fused order's scan workgroup: G groups x R RHS
 constexpr int kScanBatchWide = 512;      // batch scan workgroup: G groups x R RHS
-constexpr int kScanBatchMaxGroups = 32;  // groups per batch scan workgroup, at most
 
 // Largest block (rows of one segment) handled by the register-resident
 // sweep; larger blocks take the streaming sweep, which keeps the forward

@@ -1061,7 +1061,6 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, TMAX>())) void k_sweep_
 // the whole-block sweep: 4 wavefronts per SIMD instead of 2, which overlap
 // their loads, passes and stores.
 constexpr int kHalfRhs = 128;        // right-hand sides per workgroup (single matrix)
-constexpr uint32_t kXcdsSweep = 8;   // XCDs of the chip (workgroups dispatched round-robin)
 
 // one work item of the halves sweep: block j of H's method partition (H.P / 2
 // blocks) x RHS right-hand sides from tile * RHS, on 2 RHS threads.  KIND:
