@@ -83,6 +83,7 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     const size_t o_a32 = take(sizeof(float) * MR), o_cp32 = take(sizeof(float) * MR);
     const size_t o_rd32 = take(sizeof(float) * MR), o_in32 = take(sizeof(float) * MR);
     const size_t o_mid = take(sizeof(double) * P);
+    const size_t o_eR = take(sizeof(float) * MR);
     const size_t nslot = std::max<size_t>(o.tw_r.size(), 1);
     const size_t o_tws = take(sizeof(double) * nslot), o_twr = take(sizeof(double) * nslot);
     const size_t o_twc = take(sizeof(double) * nslot), o_twe = take(sizeof(double) * nslot);
@@ -137,6 +138,7 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     pad32(o_rd32, o.rd64, 1.0f);
     pad32(o_in32, in, 0.0f);
     if (!o.mid_inv.empty()) put(o_mid, o.mid_inv.data(), sizeof(double) * P);
+    if (!o.eR.empty()) pad32(o_eR, o.eR, 0.0f);
     if (!o.tw_r.empty()) {
         put(o_tws, o.tw_s.data(), sizeof(double) * nslot);
         put(o_twr, o.tw_r.data(), sizeof(double) * nslot);
@@ -172,6 +174,7 @@ DevTables append_image(const HostTables& o, int32_t WP, std::vector<unsigned cha
     d.rd32 = (float*)o_rd32;
     d.in32 = (float*)o_in32;
     d.mid_inv = (double*)o_mid;
+    d.eR32 = (float*)o_eR;
     d.tw_s = (double*)o_tws;
     d.tw_c = (double*)o_twc;
     d.tw_r = (double*)o_twr;
@@ -192,7 +195,7 @@ void rebase(DevTables& d, void* mem) {
     shift(d.rd32, b); shift(d.in32, b);
     shift(d.l64, b); shift(d.inl64, b); shift(d.l32, b); shift(d.inl32, b);
     shift(d.mid_inv, b);
-    shift(d.tw_s, b); shift(d.tw_c, b); shift(d.tw_r, b); shift(d.tw_e, b);
+    shift(d.eR32, b); shift(d.tw_s, b); shift(d.tw_c, b); shift(d.tw_r, b); shift(d.tw_e, b);
 }
 
 int upload_image(const std::vector<unsigned char>& img, void** out) {

@@ -67,6 +67,10 @@ struct DevTables {
     // row, r: 1 / pivot, c: coupling to the next slot's row (m after the
     // last slot) times r, e: eliminated response to the outer boundary
     // value
+    // half-block partitions, per row of a right half (zero elsewhere): its
+    // zero-boundary top-down elimination of a unit value at the middle row
+    // (FP32; the refined sweep's correction of x_m enters through it)
+    float* eR32 = nullptr;
     double* tw_s = nullptr;
     double* tw_r = nullptr;
     double* tw_c = nullptr;
@@ -86,6 +90,7 @@ struct HostTables {
     int32_t general = 0;                   // 1: non-symmetric A (by similarity)
     std::vector<double> mid_inv;           // half-block partitions only (half_tables)
     std::vector<double> tw_s, tw_r, tw_c, tw_e;   // half-block partitions: twisted slots
+    std::vector<double> eR;                // half-block partitions: right halves' response to m
 };
 
 int host_prepare(const double* a, const double* b, int64_t M, int32_t P,

@@ -1214,15 +1214,12 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
             const double dm = (s_q2[c] - a_r * s_q2[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
             if (h == 1) {
                 // dm enters the right half's first row: the eliminated
-                // response to it, row by row
-                const cptr<float> inl32 = cst((GEN ? H.inl32 : H.in32) + i0) + z;
+                // response to it (table eR32; zero on phantom rows' entries
+                // past the block is not needed: they never feed real rows)
+                const cptr<float> eR = cst(H.eR32 + i0) + z;
                 const float dmf = (float)dm;
-                float e = -(float)cst(GEN ? H.l64 : H.a64)[m] * rd32[0];
 #pragma unroll
-                for (int r = 0; r < TM; ++r) {
-                    if (r > 0) e = -inl32[r - 1] * e * rd32[r];
-                    w[r] = fmaf(dmf, e, w[r]);
-                }
+                for (int r = 0; r < TM; ++r) w[r] = fmaf(dmf, eR[r], w[r]);
             }
             carried_back_sub<TM>(H, i0, w, h == 0 ? dm : 0.0,
                                  h == 0 ? cst(H.a64)[m - 1] * (double)rd32[TM - 1] : 0.0, x);

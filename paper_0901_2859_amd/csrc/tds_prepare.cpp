@@ -339,6 +339,7 @@ int half_tables(const HostTables& o, int32_t lead, HostTables& h) {
     h.mid_inv.assign(h.P, 0.0);
     const size_t slots = 2 * (size_t)P * (size_t)lead;
     h.tw_s.assign(slots, 0.0);
+    h.eR.assign(M, 0.0);
     h.tw_r.assign(slots, 1.0);
     h.tw_c.assign(slots, 0.0);
     h.tw_e.assign(slots, 0.0);
@@ -393,6 +394,18 @@ int half_tables(const HostTables& o, int32_t lead, HostTables& h) {
                 h.tw_c[base + k] = (double)c;
                 h.tw_e[base + k] = (double)e;
                 first = false;
+            }
+        }
+        // the right half's top-down elimination of a unit value at m (its
+        // zero-boundary tables): e_0 = -A[m+1][m] / p_0, e_k = -A[i][i-1]
+        // e_{k-1} / p_k
+        {
+            wide c = 0.0L, e = 0.0L;
+            for (int64_t i = m + 1; i <= b1; ++i) {
+                const wide d = (wide)bb[i] - (i > m + 1 ? (wide)lo[i - 1] * c : 0.0L);
+                c = i < b1 ? (wide)up[i] / d : 0.0L;
+                e = -(wide)lo[i - 1] * (i > m + 1 ? e : 1.0L) / d;
+                h.eR[i] = (double)e;
             }
         }
     }
