@@ -1214,8 +1214,8 @@ __device__ __forceinline__ void halves_item(const DevTables& H, const Fin* __res
             const double dm = (s_q2[c] - a_r * s_q2[RHS + c]) * cst(H.mid_inv)[2 * j + 1];
             if (h == 1) {
                 // dm enters the right half's first row: the eliminated
-                // response to it (table eR32; zero on phantom rows' entries
-                // past the block is not needed: they never feed real rows)
+                // response to it (table eR32; rows past the half's last row
+                // read entries of other rows, but never feed a real row)
                 const cptr<float> eR = cst(H.eR32 + i0) + z;
                 const float dmf = (float)dm;
 #pragma unroll
