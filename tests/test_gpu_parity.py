@@ -150,23 +150,25 @@ def test_residual_kernel_matches_oracle_routine():
             assert np.allclose(eta, want["eta"], rtol=1e-6, atol=0), (scale, mode)
 
 
-def test_poisson_series_full_size():
-    # full 4096 x 4096 workload in the launch configuration the benchmark
-    # times, every column against the oracle
+@pytest.mark.parametrize("order", ["recurrence", "dense"])
+def test_poisson_series_full_size(order):
+    # full 4096 x 4096 workload, P = 64, every column against the oracle, in
+    # both interface orders the autotuner chooses between (it has taken the
+    # recurrences here, the dense product in earlier measurements)
     w = wl.poisson_series()
     a, b, F32 = w["a"], w["b"], w["F"]
     Fw = F32.astype(np.float64)
     ref = oracle.thomas(a, b, Fw)
     tol = _parity.tol64(a, b, Fw, ref, w["P"])
     plan = t.Plan(a, b, w["P"])
-    plan.set_interface("dense")                # the benchmark's order at P = 64
+    plan.set_interface(order)
     Fs = torch.from_numpy(F32).to(DEV)
     for mode, Fin, passes in (("f32_refined", Fs, 1), ("f32_refined", Fs, 2),
                               ("f32_wide", Fs, 2), ("f64", Fs.double(), 2)):
-        print(f"full size mode={mode} passes={passes}", flush=True)
-        plan.set_refinement(passes)            # 1: the benchmark's count here
+        print(f"full size order={order} mode={mode} passes={passes}", flush=True)
+        plan.set_refinement(passes)            # 1: the autotuner's count here
         Xh = plan.solve(Fin, mode=mode).cpu().numpy()
-        what = f"poisson 4096x4096 {mode} passes={passes}"
+        what = f"poisson 4096x4096 {order} {mode} passes={passes}"
         _parity.check(Xh, ref, tol, what)
         _parity.check_residual(a, b, Fw, Xh, ref, what)
         del Xh
@@ -229,14 +231,14 @@ def test_changing_n_and_graph_replays():
 
 
 @pytest.mark.parametrize("M,N,P,offset", [
-    # blocks of 62-64 rows: the refined sweep's pipelined kernel, whose
-    # wavefronts walk several tiles of 64 right-hand sides each
+    # blocks of 62-64 rows (the refined halves sweep, 128 right-hand sides
+    # per workgroup) over many tiles, with ragged tails and unaligned F
     (2000, 4099, 32, 0),    # odd N: 4-byte row loads, ragged last tile
     (2000, 4100, 32, 0),    # 8-byte row loads except in the ragged last tile
     (4096, 2048, 64, 0),    # full tiles, two per wavefront
     (1000, 1024, 16, 1),    # F 4 bytes past an 8-byte boundary: 4-byte loads
 ])
-def test_refined_many_tiles_per_wavefront(M, N, P, offset):
+def test_refined_many_tiles(M, N, P, offset):
     print(f"case M={M} N={N} P={P} offset={offset}", flush=True)
     rng = np.random.default_rng(M + 7 * N + P)
     a, b = _rand(rng, M)
