@@ -65,6 +65,9 @@ def parse():
                    choices=["auto", "recurrence", "dichotomy", "dense"],
                    help="evaluation order of the interface values (single-matrix workloads); "
                         "auto: the autotuner's measured choice")
+    p.add_argument("--batch-fused", type=int, default=8,
+                   help="lag (tiles of 256 right-hand sides) of the uneven batch's one-launch "
+                        "order, timed beside its separate launches (0: not timed)")
     p.add_argument("--fused", type=int, default=None,
                    help="lag of the fused order (single-matrix workloads; 0: three launches "
                         "per solve); default: the autotuner's measured choice")
@@ -360,6 +363,18 @@ class Batch:
             self.plan.solve(Fs, Xs, mode=mode)
 
         r = time_steps(solve, 1, steps, warmup, graph_for(args, "batch"), self.plan, torch)
+        # the one-launch order of the same batch (tdsolve_batch_set_fused;
+        # bitwise the same X), timed the same way, when every matrix has
+        # blocks of at most 32 rows (otherwise the library would run the
+        # separate launches)
+        r["one_launch"] = None
+        if args.batch_fused > 0 and all(-(-m // p) <= 32 for m, p in zip(self.Ms, self.P)):
+            self.plan.set_fused(args.batch_fused)
+            f = time_steps(solve, 1, max(10, steps // 2), max(3, warmup // 2),
+                           graph_for(args, "batch"), self.plan, torch)
+            self.plan.set_fused(0)
+            r["one_launch"] = {"lag_tiles": args.batch_fused,
+                               "ms_per_step": round(f["ms_per_step"], 5), "launch": f["launch"]}
         # residuals of every matrix of the batch: the largest normwise
         # backward error from the library (tdsolve_status, which recomputes
         # the last batch solve's residuals), and the relative 2-norm residual
@@ -607,6 +622,8 @@ def workload_report(name, args, t, wl, torch, dev, mode, steps, warmup, passes=N
         "compare": compare,
         "cpu_baseline": cpu,
     }
+    if "one_launch" in main_r:
+        rep["one_launch"] = main_r["one_launch"]
     modes = dict(compare)
     modes[mode] = main_r
     rep["equal_residual"] = equal_residual(modes)

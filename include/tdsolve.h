@@ -367,6 +367,24 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a,
 int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
                          const int64_t* N, int32_t mode, void* stream);
 
+/* One-launch order of tdsolve_batch_series (the steps of Algorithm 3 for
+ * every matrix of the batch in one grid).  lag == 0 (default): the launches
+ * of tdsolve_batch_series.  lag >= 1: one launch (after a small one that
+ * clears its counters) whose workgroups take the work items of all
+ * matrices in ticket order, tile by tile of 256 right-hand sides of each
+ * matrix in turn: the beta weights of tile s, the interface values of tile
+ * s - lag (each waiting until the weights of its tile are published) and
+ * the block sweeps of tile s - 2 lag (each waiting until its tile's
+ * interface values are published).  Waits are only on earlier tickets and
+ * bounded.  Same work items and arithmetic as the separate launches:
+ * bitwise the same X.  Taken when every matrix with right-hand sides has
+ * blocks of at most 32 rows; otherwise the separate launches run.  Its
+ * ticket table (8 bytes per work item) is uploaded with the descriptors,
+ * and its counters (2 + 2 T lines of 256 bytes for T tiles) sit in the
+ * handle's work buffer.  Phase timing reports the launch as the sweep
+ * phase.  Errors: TDS_EINVAL (not a batch handle, lag outside 0..64). */
+int tdsolve_batch_set_fused(tds_handle hb, int32_t lag);
+
 /* Measured block counts for a batch.  Each matrix gets 32 or 64 rows per
  * block (P[k] = ceil(M[k] / rows) within the method's limits; the batch
  * runs one launch of each kernel per register row bucket, and with 64 rows

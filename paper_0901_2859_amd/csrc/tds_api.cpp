@@ -8,6 +8,7 @@
 #include <cmath>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "tdsolve.h"
@@ -28,7 +29,8 @@ struct tds_plan {
     int32_t iface = TDS_IFACE_RECURRENCE;   // interface-step evaluation order
     double* dense_K = nullptr;   // Theorem 2 coefficient table (TDS_IFACE_DENSE)
     int32_t dense_Pc = 0, dense_Mr = 0;
-    int32_t fuse_lag = 0;        // fused order: sweeps this many tiles behind (0: three kernels)
+    int32_t fuse_lag = 0;        // fused order: sweeps this many tiles (batch: matrices)
+                                 //   behind (0: three kernels)
     int32_t fuse_cols = 0;       // fused order: right-hand sides per tile
     int device = 0;
     void* work = nullptr;        // grows with N
@@ -45,8 +47,10 @@ struct tds_plan {
     std::vector<DevTables> devs_h;       // half-block tables of the 64-row matrices, when
                                          //   every one of them has them
     std::vector<BatchDesc> desc;         // last descriptors uploaded
-    BatchDesc* d_desc = nullptr;         // descriptors, then the item owner maps
+    BatchDesc* d_desc = nullptr;         // descriptors, then the item owner maps and
+                                         //   the one-launch order's ticket table
     size_t desc_bytes = 0;               // capacity of d_desc
+    int32_t desc_lag = 0;                // one-launch lag the uploaded ticket table is for
     // the last series call, for tdsolve_status
     bool have_last = false;
     int32_t last_mode = 0, last_passes = 0;
@@ -667,6 +671,12 @@ int tdsolve_set_fused(tds_handle h, int32_t lag, int32_t tile) {
     return TDS_OK;
 }
 
+int tdsolve_batch_set_fused(tds_handle h, int32_t lag) {
+    if (!h || !h->is_batch || lag < 0 || lag > kFuseMaxLag) return TDS_EINVAL;
+    h->fuse_lag = lag;
+    return TDS_OK;
+}
+
 int tdsolve_set_refinement(tds_handle h, int32_t passes) {
     if (!h || passes < 0 || passes > 8) return TDS_EINVAL;
     h->passes = passes;
@@ -812,6 +822,17 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a, const double* const
     return TDS_OK;
 }
 
+// work items of one batch matrix in the one-launch order: beta or sweep
+// items (a block x 256 right-hand sides each) and interface items (2^(lgR-1)
+// right-hand sides each on a 256-thread workgroup; lgR >= 3 since G <= 64)
+static int64_t fused_items(const BatchDesc& d) {
+    return (int64_t)d.T.P * ((d.N + kWG - 1) / kWG);
+}
+static int64_t fused_scans(const BatchDesc& d) {
+    const int lg = d.lgR - 1;
+    return (d.N + ((int64_t)1 << lg) - 1) >> lg;
+}
+
 int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, const int64_t* N,
                          int32_t mode, void* stream) {
     if (!h || !h->is_batch || !F || !X || !N || !valid_mode(mode)) return TDS_EINVAL;
@@ -840,7 +861,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         d.item0 = grp_items[grp];
         d.scan0 = scans;
         batch_scan_shape(t.P, &d.per, &d.G, &d.lgR);
-        d.pad_ = 0;
+        d.tile0 = 0;
         const size_t nb = align256(sizeof(double) * (size_t)t.P * (size_t)n);
         d.betaR = (double*)bytes;
         d.betaL = (double*)(bytes + nb);
@@ -857,6 +878,25 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         return TDS_OK;
     }
     if (items > 0x7fffffffLL || scans > 0x7fffffffLL) return TDS_EUNSUPPORTED;
+    // the one-launch order (tdsolve_batch_set_fused) when every matrix with
+    // work is in the 32-row bucket: its tickets (per matrix the beta and the
+    // sweep items, and the interface items on 256-thread workgroups) and its
+    // counters behind the work slices
+    const bool fused = h->fuse_lag > 0 && grp_items[1] == 0 && K < (1 << 30);
+    int64_t tickets = 0, ftiles = 0;
+    size_t sync_off = 0;
+    if (fused) {
+        for (BatchDesc& d : desc) {
+            d.tile0 = (int32_t)std::min<int64_t>(ftiles, INT32_MAX);
+            if (d.N == 0) continue;
+            ftiles += (d.N + kWG - 1) / kWG;
+            tickets += fused_items(d);
+            if (d.T.P > 1) tickets += fused_items(d) + fused_scans(d);
+        }
+        if (tickets > 0x7fffffffLL || ftiles > 0x7fffffffLL) return TDS_EUNSUPPORTED;
+        sync_off = align256(bytes);
+        bytes = sync_off + align256(sizeof(int) * (size_t)fused_batch_sync_ints(ftiles));
+    }
     int rc = ensure_work(h, std::max<size_t>(bytes, 256));
     if (rc) return rc;
     for (auto& d : desc) {
@@ -871,8 +911,10 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     // every interface item, so that a workgroup finds its matrix by one load.
     const size_t dbytes = align256(sizeof(BatchDesc) * desc.size());
     const size_t ibytes = align256(sizeof(int32_t) * (size_t)items);
-    const size_t total = dbytes + ibytes + sizeof(int32_t) * (size_t)std::max<int64_t>(scans, 1);
-    const bool same = desc.size() == h->desc.size() &&
+    const size_t sbytes = align256(sizeof(int32_t) * (size_t)std::max<int64_t>(scans, 1));
+    const size_t total = dbytes + ibytes + sbytes + sizeof(uint64_t) * (size_t)tickets;
+    const int32_t lag = fused ? h->fuse_lag : 0;
+    const bool same = desc.size() == h->desc.size() && lag == h->desc_lag &&
                       memcmp(desc.data(), h->desc.data(), sizeof(BatchDesc) * desc.size()) == 0;
     if (!same) {
         std::vector<unsigned char> img;
@@ -895,6 +937,42 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
                 for (int64_t i = 0; i < ns; ++i) os[d.scan0 + i] = k;
             }
         }
+        if (fused) {
+            // stages: the tiles of kWG columns of every matrix, matrix by
+            // matrix; stage st holds the interface items of tile st - lag,
+            // the sweep items of tile st - 2 lag and the beta items of tile st
+            std::vector<std::pair<int32_t, int64_t>> stage;     // (matrix, tile)
+            stage.reserve((size_t)ftiles);
+            for (int32_t k = 0; k < K; ++k)
+                for (int64_t c = 0; c < (desc[k].N + kWG - 1) / kWG; ++c) stage.push_back({k, c});
+            uint64_t* tk = (uint64_t*)(img.data() + dbytes + ibytes + sbytes);
+            int64_t q = 0;
+            auto put = [&](uint64_t kind, int64_t k, int64_t i) {
+                tk[q++] = kind << 62 | (uint64_t)k << 32 | (uint64_t)i;
+            };
+            // block-major items of one tile: j tiles + c for every block j
+            auto blocks = [&](uint64_t kind, int64_t st) {
+                const int32_t k = stage[st].first;
+                const int64_t c = stage[st].second, tiles = (desc[k].N + kWG - 1) / kWG;
+                for (int64_t j = 0; j < desc[k].T.P; ++j) put(kind, k, j * tiles + c);
+            };
+            const int64_t S = (int64_t)stage.size();
+            for (int64_t st = 0; st < S + 2 * lag; ++st) {
+                const int64_t si = st - lag, ss = st - 2 * lag;
+                if (si >= 0 && si < S && desc[stage[si].first].T.P > 1) {
+                    // the interface items whose 2^(lgR-1) columns lie in tile si
+                    const BatchDesc& d = desc[stage[si].first];
+                    const int lg = d.lgR - 1;
+                    const int64_t c0 = stage[si].second * kWG;
+                    const int64_t c1 = std::min<int64_t>(c0 + kWG, d.N);
+                    for (int64_t i = c0 >> lg; i < (c1 + ((int64_t)1 << lg) - 1) >> lg; ++i)
+                        put(kFusedIface, stage[si].first, i);
+                }
+                if (ss >= 0 && ss < S) blocks(kFusedSweep, ss);
+                if (st < S && desc[stage[st].first].T.P > 1) blocks(kFusedBeta, st);
+            }
+            if (q != tickets) return TDS_EHIP;     // the counts above disagree
+        }
         if (h->desc_bytes < total) {
             if (h->d_desc) {
                 if (hipDeviceSynchronize() != hipSuccess) return TDS_EHIP;
@@ -910,11 +988,27 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         if (hipMemcpy(h->d_desc, img.data(), total, hipMemcpyHostToDevice) != hipSuccess)
             return TDS_EHIP;
         h->desc = desc;
+        h->desc_lag = lag;
     }
     const int32_t* own_items = (const int32_t*)((const unsigned char*)h->d_desc + dbytes);
     const int32_t* own_scans = (const int32_t*)((const unsigned char*)h->d_desc + dbytes + ibytes);
     KTime* tm = timing_slot(h);
     if (h->timing && !tm) return TDS_EHIP;
+    if (fused) {
+        // one launch, timed as the sweep phase
+        if (tm) {
+            empty_phase(h, 0);
+            empty_phase(h, 1);
+        }
+        const uint64_t* tk =
+            (const uint64_t*)((const unsigned char*)h->d_desc + dbytes + ibytes + sbytes);
+        if (launch_fused_batch(h->d_desc, tk, tickets, ftiles, mode, h->passes,
+                               (int*)(general_of(h) + sync_off), (hipStream_t)stream,
+                               tm ? tm + 2 : nullptr) != hipSuccess)
+            return TDS_EHIP;
+        remember(h, F, X, N, K, mode);
+        return TDS_OK;
+    }
     if (tm && scans == 0) empty_phase(h, 1);
     if (launch_batch(h->d_desc, own_items, own_scans, grp_items[0], grp_items[1], scans, mode,
                      h->passes, h->has_halves, tm, (hipStream_t)stream) != hipSuccess)

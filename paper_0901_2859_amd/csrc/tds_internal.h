@@ -67,14 +67,14 @@ struct DevTables {
     // row, r: 1 / pivot, c: coupling to the next slot's row (m after the
     // last slot) times r, e: eliminated response to the outer boundary
     // value
-    // half-block partitions, per row of a right half (zero elsewhere): its
-    // zero-boundary top-down elimination of a unit value at the middle row
-    // (FP32; the refined sweep's correction of x_m enters through it)
-    float* eR32 = nullptr;
     double* tw_s = nullptr;
     double* tw_r = nullptr;
     double* tw_c = nullptr;
     double* tw_e = nullptr;
+    // half-block partitions, per row of a right half (zero elsewhere): its
+    // zero-boundary top-down elimination of a unit value at the middle row
+    // (FP32; the refined sweep's correction of x_m enters through it)
+    float* eR32 = nullptr;
 };
 
 // Host-side FP64 preliminary step.  Returns a tds_status code.
@@ -194,7 +194,8 @@ struct BatchDesc {
     int32_t per;
     int32_t G;
     int32_t lgR;
-    int32_t pad_;
+    int32_t tile0;     // one-launch order: the matrix's first tile of kWG columns
+                       //   among the tiles of all matrices
     DevTables H;       // half-block tables (half_tables), when the batch uses them
 };
 
@@ -215,6 +216,20 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items,
                         const int32_t* own_scans, int64_t items32, int64_t items64,
                         int64_t scans, int mode, int passes, bool halves,
                         const KTime* tm, hipStream_t s);
+
+// The same three steps for all matrices of a batch in one launch (after a
+// small one that clears `sync`), every matrix in the 32-row bucket.  tk:
+// device array of `tickets` item codes in ticket order (kind << 62 | matrix
+// << 32 | index of the item within its matrix; kinds kFusedBeta,
+// kFusedIface, kFusedSweep), the interface items on 256-thread workgroups
+// (BatchDesc::lgR - 1); S: the number of tiles of kWG columns over all
+// matrices (BatchDesc::tile0 numbers them).  sync: fused_batch_sync_ints(S)
+// device ints.  `tm` (may be null) times the launch.
+constexpr uint64_t kFusedBeta = 0, kFusedIface = 1, kFusedSweep = 2;
+int64_t fused_batch_sync_ints(int64_t S);
+hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t tickets,
+                              int64_t S, int mode, int passes, int* sync, hipStream_t s,
+                              const KTime* tm);
 
 // uniform[-1, 1) values from a counter-based generator (timing inputs)
 hipError_t launch_fill_uniform(void* p, int64_t n, bool f32, uint64_t seed, hipStream_t s);

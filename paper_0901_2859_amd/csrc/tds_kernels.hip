@@ -272,7 +272,7 @@ __device__ __forceinline__ void beta_item_vec(const DevTables& T, const Fin* __r
 // of the launches and no LDS reduction.  Each wavefront forms the four
 // quarter sums of beta_item separately and adds them in the order of its
 // reduction, so the weights are bitwise those of a single-matrix plan.
-template <int TMAX, typename Fin>
+template <int TMAX, typename Fin, bool COH = false>
 __device__ __forceinline__ void beta_rows_item(const DevTables& T, const Fin* __restrict__ F,
                                                int64_t N, int32_t j, int64_t n0,
                                                double* __restrict__ betaR,
@@ -308,8 +308,8 @@ __device__ __forceinline__ void beta_rows_item(const DevTables& T, const Fin* __
         }
     }
     if (!live) return;
-    if (j < T.P - 1) betaR[(int64_t)j * N + n0 + lane] = bR;
-    if (j > 0) betaL[(int64_t)j * N + n0 + lane] = bL;
+    if (j < T.P - 1) st_w<COH>(&betaR[(int64_t)j * N + n0 + lane], bR);
+    if (j > 0) st_w<COH>(&betaL[(int64_t)j * N + n0 + lane], bL);
 }
 
 // ==========================================================================
@@ -909,7 +909,7 @@ __device__ __forceinline__ void sweep_body(const Fin (&f)[TMAX], Xout* __restric
     }
 }
 
-template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN>
+template <int TMAX, typename Fin, typename Xout, int KIND, bool GEN, bool COH = false>
 __device__ __forceinline__ void sweep_item(const DevTables& T, const Fin* __restrict__ F,
                                            Xout* __restrict__ X, int64_t N, int32_t j,
                                            int64_t tile, const double* __restrict__ xsep,
@@ -920,8 +920,8 @@ __device__ __forceinline__ void sweep_item(const DevTables& T, const Fin* __rest
     const int cnt = (int)(seg_hi - i0);
     const int64_t n = tile * kWG + threadIdx.x;
     if (n >= N) return;
-    const double xl = (j > 0) ? xsep[(int64_t)(j - 1) * N + n] : 0.0;
-    const double xr = (j < P - 1) ? xsep[(int64_t)j * N + n] : 0.0;
+    const double xl = (j > 0) ? ld_w<COH>(&xsep[(int64_t)(j - 1) * N + n]) : 0.0;
+    const double xr = (j < P - 1) ? ld_w<COH>(&xsep[(int64_t)j * N + n]) : 0.0;
     const double cl = (j > 0) ? cst(GEN ? T.l64 : T.a64)[i0 - 1] : 0.0;   // A[i0][i0-1]
     const double cr = (j < P - 1) ? cst(T.a64)[seg_hi - 1] : 0.0; // A[i1][i1+1]
     if (j > 0) store_x(&X[seg_lo * N + n], (Xout)xl);
@@ -1566,6 +1566,72 @@ __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDe
                                        s_f, s_q);
 }
 
+// The uneven batch in one launch (tdsolve_batch_set_fused): the beta,
+// interface and sweep items of every matrix in one grid, taken in ticket
+// order.  Stages are the tiles of kWG columns of every matrix, matrix by
+// matrix: stage s holds the interface items of tile s - LI, the sweep items
+// of tile s - LS and the beta items of tile s (LS = 2 LI), and the host
+// writes the item of every ticket into tk (the kind in bits 62-63, the
+// matrix in bits 32-61, the item's index within its matrix in bits 0-31).
+// An interface item waits until the P beta items of its tile have published
+// their weights, a sweep item until the interface items of its tile have
+// published their values; every wait is on smaller tickets, so the launch
+// cannot deadlock (the argument of k_fused), and every wait is bounded.
+// The items are those of k_beta_batch, k_iface_batch (on 256 threads: half
+// its right-hand sides per workgroup, the same groups of blocks, so bitwise
+// the same values; 2^lgR divides kWG, so an item never spans two tiles) and
+// k_sweep_batch, so X is bitwise that of the separate launches.  Matrices
+// whose blocks fit 32 rows.  sync: lines of kSyncStride ints: [0] the
+// ticket, [1] the error word, [2, 2 + S) the beta counters of the S tiles,
+// [2 + S, 2 + 2S) their interface counters; zero before the launch.
+template <typename Fin, typename Xout, int KIND>
+__global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, 32>())) void k_fused_batch(
+    const BatchDesc* __restrict__ D, const uint64_t* __restrict__ tk, int64_t S, int passes,
+    int* __restrict__ sync) {
+    // LDS: the refined sweep's F (32 rows x 256 floats) or the interface scan
+    constexpr int LSW = KIND == kSweepRefined ? 32 * kWG / 2 : 1;
+    __shared__ double smem[LSW > kFuseScanLds ? LSW : kFuseScanLds];
+    __shared__ int32_t s_ticket;
+    if (threadIdx.x == 0)
+        s_ticket = __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int32_t ticket = __builtin_amdgcn_readfirstlane(s_ticket);
+    const uint64_t code = cst(tk)[ticket];
+    const uint64_t kind = code >> 62;
+    const int32_t k = (int32_t)((code >> 32) & 0x3fffffffu);
+    const int64_t local = (int64_t)(code & 0xffffffffu);
+    const BatchDesc d = D[k];    // uniform, before any store: scalar loads
+    int* err = sync + kSyncStride;
+    int* beta_done = sync + 2 * kSyncStride;            // + tile * kSyncStride
+    int* iface_done = sync + (2 + S) * kSyncStride;
+    const int64_t tiles = (d.N + kWG - 1) / kWG;
+    const int lgR = d.lgR - 1;                  // G R <= 256 (k_iface_batch: <= 512)
+    if (kind == kFusedBeta) {
+        const int64_t tau = local % tiles;
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kBetaRhs);
+        beta_rows_item<32, Fin, true>(d.T, (const Fin*)d.F, d.N, (int32_t)(local / tiles),
+                                      tau * kWG + wv * kBetaRhs, d.betaR, d.betaL);
+        fuse_signal(beta_done + (d.tile0 + tau) * kSyncStride);
+    } else if (kind == kFusedIface) {
+        const int64_t tau = (local << lgR) / kWG;
+        fuse_wait(beta_done + (d.tile0 + tau) * kSyncStride, d.T.P, err);
+        iface_item<kScanMaxPer, true>(d.T, d.N, d.per, d.G, d.betaR, d.betaL, d.xsep, local,
+                                      smem, lgR);
+        fuse_signal(iface_done + (d.tile0 + tau) * kSyncStride);
+    } else {
+        const int64_t tau = local % tiles;
+        if (d.T.P > 1) {
+            // the interface items of columns tau kWG .. min((tau + 1) kWG, N) - 1
+            const int64_t c1 = min((tau + 1) * kWG, d.N);
+            const int64_t want = ((c1 + ((int64_t)1 << lgR) - 1) >> lgR) - ((tau * kWG) >> lgR);
+            fuse_wait(iface_done + (d.tile0 + tau) * kSyncStride, (int)want, err);
+        }
+        sweep_item<32, Fin, Xout, KIND, false, true>(d.T, (const Fin*)d.F, (Xout*)d.X, d.N,
+                                                     (int32_t)(local / tiles), tau, d.xsep,
+                                                     passes, (float*)smem);
+    }
+}
+
 // ==========================================================================
 // launchers
 
@@ -1936,6 +2002,39 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items, const int3
     }
     if (items32 > 0) batch_sweep<32>(D, own_items, items32, mode, passes, false, s, p1[2]);
     if (items64 > 0) batch_sweep<64>(D, own64, items64, mode, passes, halves, s, p2[2]);
+    return hipGetLastError();
+}
+
+int64_t fused_batch_sync_ints(int64_t S) { return kSyncStride * (2 + 2 * S); }
+
+hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t tickets, int64_t S,
+                              int mode, int passes, int* sync, hipStream_t s, const KTime* tm) {
+    if (tickets == 0) return hipSuccess;
+    if (tickets > INT32_MAX || !sync || !tk) return hipErrorInvalidValue;
+    const int64_t nsync = fused_batch_sync_ints(S);
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nsync + kWG - 1) / kWG)), dim3(kWG), 0, s,
+                       sync, nsync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g((unsigned)tickets);
+    switch (mode) {
+        case TDS_F64:
+            launch_k(k_fused_batch<double, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk, S,
+                     passes, sync);
+            break;
+        case TDS_F32_WIDE:
+            launch_k(k_fused_batch<float, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk, S,
+                     passes, sync);
+            break;
+        case TDS_F32:
+            launch_k(k_fused_batch<float, float, kSweep32>, g, dim3(kWG), 0, s, tm, D, tk, S,
+                     passes, sync);
+            break;
+        default:
+            launch_k(k_fused_batch<float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D, tk,
+                     S, passes, sync);
+            break;
+    }
     return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ SYMBOLS = [
     "tdsolve_timing_read", "tdsolve_autotune", "tdsolve_batch_autotune", "tdsolve_autotune_plan",
     "tdsolve_prepare_host_general", "tdsolve_set_interface", "tdsolve_dense_table_host",
     "tdsolve_status", "tdsolve_strided_copy", "tdsolve_series_noalloc", "tdsolve_set_fused",
+    "tdsolve_batch_set_fused",
 ]
 
 _lib = None
@@ -79,6 +80,7 @@ def lib():
     L.tdsolve_residual.argtypes = [vp, vp, vp, i64, i32, vp, vp]
     L.tdsolve_set_refinement.argtypes = [vp, i32]
     L.tdsolve_set_fused.argtypes = [vp, i32, i32]
+    L.tdsolve_batch_set_fused.argtypes = [vp, i32]
     L.tdsolve_set_interface.argtypes = [vp, i32]
     L.tdsolve_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.tdsolve_prepare_host.argtypes = [dp, dp, i64, i32, dp, dp, dp, dp, dp, dp]
@@ -424,6 +426,13 @@ class BatchPlan:
 
     def set_refinement(self, passes: int):
         _check(lib().tdsolve_set_refinement(self._h, int(passes)), "tdsolve_set_refinement")
+
+    def set_fused(self, lag: int):
+        """The one-launch order (every matrix's items in one grid, the
+        interface items `lag` tiles of 256 right-hand sides and the sweeps 2
+        `lag` tiles behind the weights; taken when every matrix has blocks
+        of at most 32 rows), or the separate launches (lag 0)."""
+        _check(lib().tdsolve_batch_set_fused(self._h, int(lag)), "tdsolve_batch_set_fused")
 
     def solve(self, F_list, X_list=None, mode="f32_refined", stream=None):
         import torch
