@@ -398,13 +398,17 @@ int tdsolve_batch_set_fused(tds_handle hb, int32_t lag);
  * TDS_F32_REFINED, *passes_out (may be NULL; 0 in other modes) receives the
  * fewest refinement passes (1..3) whose largest normwise backward error
  * (tdsolve_status) stays within 1.25 times that of the same batch solved in
- * FP64 arithmetic (TDS_F32_WIDE).  Allocation, synchronisation and errors as
- * tdsolve_autotune. */
+ * FP64 arithmetic (TDS_F32_WIDE).  Last, when every matrix got 32 rows per
+ * block, the launch order: the separate launches and the one-launch order
+ * (tdsolve_batch_set_fused) at lags 4, 8 and 16, timed with those passes in
+ * interleaved rounds; the chosen lag (0: separate launches) goes to *lag_out
+ * (may be NULL) and its milliseconds per call to *ms_out.  Allocation,
+ * synchronisation and errors as tdsolve_autotune. */
 int tdsolve_batch_autotune(int32_t K, const double* const* a,
                            const double* const* b, const int64_t* M,
                            const int64_t* N, int32_t mode, int32_t reps,
-                           int32_t* P_out, int32_t* passes_out, double* ms_out,
-                           void* stream);
+                           int32_t* P_out, int32_t* passes_out, int32_t* lag_out,
+                           double* ms_out, void* stream);
 
 /* Scaled strided copy dst = alpha * src of an S x M x L array of doubles
  * (f64 != 0) or floats, for the drivers that move the series between a

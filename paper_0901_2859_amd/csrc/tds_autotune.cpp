@@ -258,7 +258,8 @@ int tdsolve_autotune_plan(const double* a, const double* b, int64_t M, int64_t N
 
 int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* const* b,
                            const int64_t* M, const int64_t* N, int32_t mode, int32_t reps,
-                           int32_t* P_out, int32_t* passes_out, double* ms_out, void* stream) {
+                           int32_t* P_out, int32_t* passes_out, int32_t* lag_out,
+                           double* ms_out, void* stream) {
     if (K < 1 || !a || !b || !M || !N || !P_out || mode < TDS_F64 || mode > TDS_F32_WIDE)
         return TDS_EINVAL;
     if (reps <= 0) reps = 5;
@@ -368,10 +369,36 @@ int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* cons
         }
         if (passes > 3) passes = 3;
     }
+    // launch order: with every matrix in the 32-row bucket, the one-launch
+    // order (tdsolve_batch_set_fused) at a few lags against the separate
+    // launches, with the chosen passes, in interleaved rounds
+    int32_t lag = 0;
+    bool all32 = true;
+    for (int32_t k = 0; k < K; ++k) all32 = all32 && rows[k] == 32;
+    if (!rc && all32) {
+        const int32_t lags[4] = {0, 4, 8, 16};
+        double t_lag[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+        for (int round = 0; round < kRounds && !rc; ++round)
+            for (int i = 0; i < 4 && !rc; ++i) {
+                double ms = 0.0;
+                rc = tdsolve_batch_set_fused(cur, lags[i]);
+                if (!rc) rc = series(cur);          // uploads the ticket table
+                if (!rc) rc = time_calls([&] { return series(cur); }, reps, s, ev, &ms);
+                t_lag[i] = std::min(t_lag[i], ms);
+            }
+        int best = 0;
+        for (int i = 1; i < 4; ++i)
+            if (t_lag[i] < t_lag[best]) best = i;
+        if (!rc) {
+            lag = lags[best];
+            cur_ms = t_lag[best];
+        }
+    }
     if (cur) tdsolve_destroy(cur);
     if (rc) return rc;
     for (int32_t k = 0; k < K; ++k) P_out[k] = blocks_for(M[k], rows[k]);
     if (passes_out) *passes_out = passes;
+    if (lag_out) *lag_out = lag;
     if (ms_out) *ms_out = cur_ms;
     return TDS_OK;
 }

@@ -98,7 +98,7 @@ def lib():
     L.tdsolve_timing_enable.argtypes = [vp, i32]
     L.tdsolve_timing_read.argtypes = [vp, vp, vp]
     L.tdsolve_autotune.argtypes = [dp, dp, i64, i64, i32, i32, vp, vp, vp]
-    L.tdsolve_batch_autotune.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.tdsolve_batch_autotune.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp]
     L.tdsolve_autotune_plan.argtypes = [dp, dp, i64, i64, i32, i32, vp, i32,
                                         ctypes.POINTER(Tuning), vp]
     for name in SYMBOLS:
@@ -557,13 +557,16 @@ def autotune(a, b, N: int, mode="f32_refined", reps: int = 5, cache: bool = True
 
 
 def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
-                   cache: bool = True, stream=None, with_passes: bool = False):
+                   cache: bool = True, stream=None, with_passes: bool = False,
+                   with_order: bool = False):
     """Block counts for an uneven batch (tdsolve_batch_autotune: 32 or 64
     rows per block for every matrix, then per class of matrices by size,
-    timed on the whole batch, and the refinement passes of the refined mode
-    chosen by accuracy).  Cached like autotune(), by device, mode and the
-    digest of the (M, N) list.  Returns (list of P, ms per batch solve), or
-    (list of P, passes, ms) with with_passes."""
+    timed on the whole batch, the refinement passes of the refined mode
+    chosen by accuracy, then the launch order).  Cached like autotune(), by
+    device, mode and the digest of the (M, N) list.  Returns (list of P, ms
+    per batch solve), (list of P, passes, ms) with with_passes, or (list of
+    P, passes, lag of the one-launch order (0: separate launches), ms) with
+    with_order."""
     m = mode_id(mode)
     K = len(b_list)
     bs = [_host_f64(b) for b in b_list]
@@ -571,22 +574,27 @@ def batch_autotune(a_list, b_list, N_list, mode="f32_refined", reps: int = 5,
     Ms = np.array([x.shape[0] for x in bs], dtype=np.int64)
     Ns = np.array([int(n) for n in N_list], dtype=np.int64)
     digest = hashlib.sha256(Ms.tobytes() + Ns.tobytes()).hexdigest()[:16]
-    key = f"batch-per-matrix|{_device_key()}|K={K}|MN={digest}|mode={m}"
+    key = f"batch-order|{_device_key()}|K={K}|MN={digest}|mode={m}"
     hit = _cache_load().get(key) if cache else None
-    if hit is not None and "passes" in hit:
-        Pl, passes, ms = [int(p) for p in hit["P"]], int(hit["passes"]), float(hit["ms"])
+    if hit is not None and "lag" in hit:
+        Pl, passes, lag = [int(p) for p in hit["P"]], int(hit["passes"]), int(hit["lag"])
+        ms = float(hit["ms"])
     else:
         ap = (ctypes.c_void_p * K)(*[x.ctypes.data for x in as_])
         bp = (ctypes.c_void_p * K)(*[x.ctypes.data for x in bs])
         Ps = np.zeros(K, dtype=np.int32)
         npass = ctypes.c_int32()
+        nlag = ctypes.c_int32()
         msv = ctypes.c_double()
         _check(lib().tdsolve_batch_autotune(K, ap, bp, _ptr(Ms), _ptr(Ns), m, int(reps),
-                                            _ptr(Ps), ctypes.byref(npass), ctypes.byref(msv),
-                                            _stream_ptr(stream)), "tdsolve_batch_autotune")
-        Pl, passes, ms = Ps.tolist(), int(npass.value), float(msv.value)
+                                            _ptr(Ps), ctypes.byref(npass), ctypes.byref(nlag),
+                                            ctypes.byref(msv), _stream_ptr(stream)),
+               "tdsolve_batch_autotune")
+        Pl, passes, lag, ms = Ps.tolist(), int(npass.value), int(nlag.value), float(msv.value)
         if cache:
-            _cache_store(key, {"P": Pl, "passes": passes, "ms": ms})
+            _cache_store(key, {"P": Pl, "passes": passes, "lag": lag, "ms": ms})
+    if with_order:
+        return Pl, passes, lag, ms
     return (Pl, passes, ms) if with_passes else (Pl, ms)
 
 

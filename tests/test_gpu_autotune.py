@@ -146,3 +146,16 @@ def test_batch_autotune_passes(tmp_path, monkeypatch):
         assert P in (max(1, min(-(-M // 32), M // 2)), max(1, min(-(-M // 64), M // 2))), (M, P)
     assert t.batch_autotune(a_l, b_l, Ns, "f32_refined", with_passes=True) == (P_l, passes, ms)
     assert t.batch_autotune(a_l, b_l, Ns, "f64", with_passes=True)[1] == 0
+    # the launch order: a lag of the one-launch order only when every
+    # matrix has 32-row blocks, and the chosen order solves as the other
+    P_l, passes, lag, ms = t.batch_autotune(a_l, b_l, Ns, "f64", with_order=True)
+    assert lag in (0, 4, 8, 16) and ms > 0
+    if lag:
+        assert all(P == max(1, min(-(-it["M"] // 32), it["M"] // 2)) for it, P in zip(items, P_l))
+    bp = t.BatchPlan(a_l, b_l, P_l)
+    Fs = [torch.from_numpy(it["F"]).to(DEV).double() for it in items]
+    X0 = bp.solve(Fs, mode="f64")
+    bp.set_fused(lag)
+    X1 = bp.solve(Fs, mode="f64")
+    for k in range(len(items)):
+        assert torch.equal(X0[k], X1[k]), k

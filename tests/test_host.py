@@ -244,7 +244,7 @@ def test_new_entry_points_reject_bad_arguments_without_gpu():
                               None) == -1                              # bad mode
     assert L.tdsolve_autotune(P_(a), P_(b), 10, 5, 0, 3, None, None, None) == -1
     assert L.tdsolve_batch_autotune(0, None, None, None, None, 0, 3, None, None, None,
-                                    None) == -1
+                                    None, None) == -1
     tun = t.Tuning()
     assert L.tdsolve_autotune_plan(P_(a), P_(b), 10, 0, 0, 0, None, 3, ctypes.byref(tun),
                                    None) == -1                         # N = 0
