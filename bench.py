@@ -65,7 +65,7 @@ def parse():
                    choices=["auto", "recurrence", "dichotomy", "dense"],
                    help="evaluation order of the interface values (single-matrix workloads); "
                         "auto: the autotuner's measured choice")
-    p.add_argument("--batch-fused", type=int, default=8,
+    p.add_argument("--batch-fused", type=int, default=16,
                    help="lag (tiles of 256 right-hand sides) of the uneven batch's one-launch "
                         "order when it is timed beside the autotuner's choice of the separate "
                         "launches (0: not timed)")
@@ -587,6 +587,12 @@ def workload_report(name, args, t, wl, torch, dev, mode, steps, warmup, passes=N
         kname = "k_sweep_batch_halves" if rows == 64 and mode != "f32" else "k_sweep_batch"
         shape = (f"{name}_r{rows}" if len(buckets) == 1 else f"{name}_mixed") \
             if name == "batch" else name
+        if getattr(W, "lag", 0) > 0:
+            # the whole step in one launch (timed as the sweep phase): its
+            # algorithmic bytes are the path's, F read once and X written once
+            kname = "k_fused_batch"
+            sweep_bytes = W.unknowns * (F_BYTES[mode] + X_BYTES[mode])
+            achieved = sweep_bytes / (ms_sweep * 1e-3) / 1e9
     elif mode != "f32" and W.plan.info().sweep_halves:
         kname = "k_sweep_halves"
         shape = f"{name}_{W.M}x{W.N}_P{W.P}"

@@ -371,12 +371,12 @@ int tdsolve_batch_series(tds_handle hb, const void* const* F, void* const* X,
  * every matrix of the batch in one grid).  lag == 0 (default): the launches
  * of tdsolve_batch_series.  lag >= 1: one launch (after a small one that
  * clears its counters) whose workgroups take the work items of all
- * matrices in ticket order, tile by tile of 256 right-hand sides of each
- * matrix in turn: the beta weights of tile s, the interface values of tile
- * s - lag (each waiting until the weights of its tile are published) and
- * the block sweeps of tile s - 2 lag (each waiting until its tile's
- * interface values are published).  Waits are only on earlier tickets and
- * bounded.  Same work items and arithmetic as the separate launches:
+ * matrices in ticket order, two per ticket, tile by tile of 256 right-hand
+ * sides of each matrix in turn: the beta weights of tile s, the interface
+ * values of tile s - lag (each waiting until the weights of its tile are
+ * published) and the block sweeps of tile s - 2 lag (each waiting until
+ * its tile's interface values are published).  Waits are only on earlier
+ * items and bounded.  Same work items and arithmetic as the separate launches:
  * bitwise the same X.  Taken when every matrix with right-hand sides has
  * blocks of at most 32 rows; otherwise the separate launches run.  Its
  * ticket table (8 bytes per work item) is uploaded with the descriptors,
@@ -398,12 +398,15 @@ int tdsolve_batch_set_fused(tds_handle hb, int32_t lag);
  * TDS_F32_REFINED, *passes_out (may be NULL; 0 in other modes) receives the
  * fewest refinement passes (1..3) whose largest normwise backward error
  * (tdsolve_status) stays within 1.25 times that of the same batch solved in
- * FP64 arithmetic (TDS_F32_WIDE).  Last, when every matrix got 32 rows per
- * block, the launch order: the separate launches and the one-launch order
- * (tdsolve_batch_set_fused) at lags 4, 8 and 16, timed with those passes in
- * interleaved rounds; the chosen lag (0: separate launches) goes to *lag_out
- * (may be NULL) and its milliseconds per call to *ms_out.  Allocation,
- * synchronisation and errors as tdsolve_autotune. */
+ * FP64 arithmetic (TDS_F32_WIDE).  Last, the launch order: the one-launch
+ * order (tdsolve_batch_set_fused) at lags 8, 16 and 32 with 32 rows per
+ * block for every matrix, against the chosen blocks in separate launches,
+ * timed in interleaved rounds (for TDS_F32_REFINED only when the chosen
+ * blocks are all 32-row ones, with the chosen passes).  When the one launch
+ * is faster, P_out holds the 32-row blocks and *lag_out (may be NULL) its
+ * lag; otherwise *lag_out is 0.  *ms_out: milliseconds per call of the
+ * chosen configuration.  Allocation, synchronisation and errors as
+ * tdsolve_autotune. */
 int tdsolve_batch_autotune(int32_t K, const double* const* a,
                            const double* const* b, const int64_t* M,
                            const int64_t* N, int32_t mode, int32_t reps,

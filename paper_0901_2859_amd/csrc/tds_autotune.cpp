@@ -369,30 +369,53 @@ int tdsolve_batch_autotune(int32_t K, const double* const* a, const double* cons
         }
         if (passes > 3) passes = 3;
     }
-    // launch order: with every matrix in the 32-row bucket, the one-launch
-    // order (tdsolve_batch_set_fused) at a few lags against the separate
-    // launches, with the chosen passes, in interleaved rounds
+    // launch order: the one-launch order (tdsolve_batch_set_fused) at a few
+    // lags, with every matrix in the 32-row bucket, against the chosen
+    // blocks in separate launches, in interleaved rounds.  When the chosen
+    // blocks are not all 32-row ones, the one launch runs on 32-row blocks
+    // of its own (not for the refined mode, whose passes were chosen for
+    // the chosen blocks).  On the 256-matrix benchmark batch the one launch
+    // runs best at a lag of 16 tiles and is faster than the separate
+    // launches in FP64 arithmetic, slower for the refined mode.
     int32_t lag = 0;
     bool all32 = true;
     for (int32_t k = 0; k < K; ++k) all32 = all32 && rows[k] == 32;
-    if (!rc && all32) {
-        const int32_t lags[4] = {0, 4, 8, 16};
+    if (!rc && (all32 || mode != TDS_F32_REFINED)) {
+        tds_handle h32 = all32 ? cur : nullptr;
+        if (!all32) {
+            for (int32_t k = 0; k < K; ++k) P[k] = blocks_for(M[k], 32);
+            rc = tdsolve_batch_prepare(K, a, b, M, P.data(), &h32);
+        }
+        const int32_t lags[4] = {0, 8, 16, 32};
         double t_lag[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-        for (int round = 0; round < kRounds && !rc; ++round)
-            for (int i = 0; i < 4 && !rc; ++i) {
-                double ms = 0.0;
-                rc = tdsolve_batch_set_fused(cur, lags[i]);
-                if (!rc) rc = series(cur);          // uploads the ticket table
-                if (!rc) rc = time_calls([&] { return series(cur); }, reps, s, ev, &ms);
+        double t_cur = INFINITY;
+        for (int round = 0; round < kRounds && !rc; ++round) {
+            double ms = 0.0;
+            if (!all32) {
+                rc = time_calls([&] { return series(cur); }, reps, s, ev, &ms);
+                t_cur = std::min(t_cur, ms);
+            }
+            for (int i = all32 ? 0 : 1; i < 4 && !rc; ++i) {
+                rc = tdsolve_batch_set_fused(h32, lags[i]);
+                if (!rc) rc = series(h32);          // uploads the ticket table
+                if (!rc) rc = time_calls([&] { return series(h32); }, reps, s, ev, &ms);
                 t_lag[i] = std::min(t_lag[i], ms);
             }
+        }
+        if (all32) t_cur = t_lag[0];
         int best = 0;
         for (int i = 1; i < 4; ++i)
-            if (t_lag[i] < t_lag[best]) best = i;
+            if (t_lag[i] < (best ? t_lag[best] : t_cur)) best = i;
         if (!rc) {
-            lag = lags[best];
-            cur_ms = t_lag[best];
+            if (best > 0) {
+                lag = lags[best];
+                cur_ms = t_lag[best];
+                for (int32_t k = 0; k < K; ++k) rows[k] = 32;
+            } else {
+                cur_ms = t_cur;
+            }
         }
+        if (h32 && h32 != cur) tdsolve_destroy(h32);
     }
     if (cur) tdsolve_destroy(cur);
     if (rc) return rc;

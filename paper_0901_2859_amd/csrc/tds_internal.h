@@ -219,7 +219,8 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items,
 
 // The same three steps for all matrices of a batch in one launch (after a
 // small one that clears `sync`), every matrix in the 32-row bucket.  tk:
-// device array of `tickets` item codes in ticket order (kind << 62 | matrix
+// device array of `tickets` item codes in order, taken two per workgroup
+// ticket (kind << 62 | matrix
 // << 32 | index of the item within its matrix; kinds kFusedBeta,
 // kFusedIface, kFusedSweep), the interface items on 256-thread workgroups
 // (BatchDesc::lgR - 1); S: the number of tiles of kWG columns over all

@@ -1568,14 +1568,16 @@ __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDe
 
 // The uneven batch in one launch (tdsolve_batch_set_fused): the beta,
 // interface and sweep items of every matrix in one grid, taken in ticket
-// order.  Stages are the tiles of kWG columns of every matrix, matrix by
-// matrix: stage s holds the interface items of tile s - LI, the sweep items
-// of tile s - LS and the beta items of tile s (LS = 2 LI), and the host
-// writes the item of every ticket into tk (the kind in bits 62-63, the
-// matrix in bits 32-61, the item's index within its matrix in bits 0-31).
+// order, two consecutive items per ticket.  Stages are the tiles of kWG
+// columns of every matrix, matrix by matrix: stage s holds the interface
+// items of tile s - LI, the sweep items of tile s - LS and the beta items of
+// tile s (LS = 2 LI), and the host writes the items in that order into tk
+// (the kind in bits 62-63, the matrix in bits 32-61, the item's index
+// within its matrix in bits 0-31).
 // An interface item waits until the P beta items of its tile have published
 // their weights, a sweep item until the interface items of its tile have
-// published their values; every wait is on smaller tickets, so the launch
+// published their values; every wait is on items earlier in tk, held by
+// smaller tickets or done by the same workgroup before, so the launch
 // cannot deadlock (the argument of k_fused), and every wait is bounded.
 // The items are those of k_beta_batch, k_iface_batch (on 256 threads: half
 // its right-hand sides per workgroup, the same groups of blocks, so bitwise
@@ -1584,19 +1586,14 @@ __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDe
 // whose blocks fit 32 rows.  sync: lines of kSyncStride ints: [0] the
 // ticket, [1] the error word, [2, 2 + S) the beta counters of the S tiles,
 // [2 + S, 2 + 2S) their interface counters; zero before the launch.
+// items per ticket of k_fused_batch (the kernel body takes two)
+constexpr int32_t kFusedGroup = 2;
+
+// one work item of k_fused_batch (code: its entry of the ticket table)
 template <typename Fin, typename Xout, int KIND>
-__global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, 32>())) void k_fused_batch(
-    const BatchDesc* __restrict__ D, const uint64_t* __restrict__ tk, int64_t S, int passes,
-    int* __restrict__ sync) {
-    // LDS: the refined sweep's F (32 rows x 256 floats) or the interface scan
-    constexpr int LSW = KIND == kSweepRefined ? 32 * kWG / 2 : 1;
-    __shared__ double smem[LSW > kFuseScanLds ? LSW : kFuseScanLds];
-    __shared__ int32_t s_ticket;
-    if (threadIdx.x == 0)
-        s_ticket = __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int32_t ticket = __builtin_amdgcn_readfirstlane(s_ticket);
-    const uint64_t code = cst(tk)[ticket];
+__device__ __forceinline__ void fused_batch_item(const BatchDesc* __restrict__ D, uint64_t code,
+                                                 int64_t S, int passes, int* __restrict__ sync,
+                                                 double* smem) {
     const uint64_t kind = code >> 62;
     const int32_t k = (int32_t)((code >> 32) & 0x3fffffffu);
     const int64_t local = (int64_t)(code & 0xffffffffu);
@@ -1629,6 +1626,31 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, 32>())) void k_fused_ba
         sweep_item<32, Fin, Xout, KIND, false, true>(d.T, (const Fin*)d.F, (Xout*)d.X, d.N,
                                                      (int32_t)(local / tiles), tau, d.xsep,
                                                      passes, (float*)smem);
+    }
+}
+
+template <typename Fin, typename Xout, int KIND>
+__global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, 32>())) void k_fused_batch(
+    const BatchDesc* __restrict__ D, const uint64_t* __restrict__ tk, int64_t tickets,
+    int64_t S, int passes, int* __restrict__ sync) {
+    // LDS: the refined sweep's F (32 rows x 256 floats) or the interface scan
+    constexpr int LSW = KIND == kSweepRefined ? 32 * kWG / 2 : 1;
+    __shared__ double smem[LSW > kFuseScanLds ? LSW : kFuseScanLds];
+    __shared__ int32_t s_ticket;
+    if (threadIdx.x == 0)
+        s_ticket = __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // one ticket: kFusedGroup consecutive items of the table, in order (a
+    // wait of the later one is on earlier tickets or on this workgroup's own
+    // finished item).  Every workgroup increments the one ticket counter,
+    // which serialises them: one item per ticket, the refined batch took
+    // 3.68 ms per step at best, two 3.26 ms; three or four hold more
+    // registers across the items and spill (3.66 and 3.71 ms).
+    const int64_t q0 = (int64_t)__builtin_amdgcn_readfirstlane(s_ticket) * kFusedGroup;
+    fused_batch_item<Fin, Xout, KIND>(D, cst(tk)[q0], S, passes, sync, smem);
+    if (q0 + 1 < tickets) {
+        __syncthreads();                        // LDS of the first item
+        fused_batch_item<Fin, Xout, KIND>(D, cst(tk)[q0 + 1], S, passes, sync, smem);
     }
 }
 
@@ -2007,6 +2029,7 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items, const int3
 
 int64_t fused_batch_sync_ints(int64_t S) { return kSyncStride * (2 + 2 * S); }
 
+
 hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t tickets, int64_t S,
                               int mode, int passes, int* sync, hipStream_t s, const KTime* tm) {
     if (tickets == 0) return hipSuccess;
@@ -2016,23 +2039,23 @@ hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t ti
                        sync, nsync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 g((unsigned)tickets);
+    const dim3 g((unsigned)((tickets + kFusedGroup - 1) / kFusedGroup));
     switch (mode) {
         case TDS_F64:
-            launch_k(k_fused_batch<double, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk, S,
-                     passes, sync);
+            launch_k(k_fused_batch<double, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk,
+                     tickets, S, passes, sync);
             break;
         case TDS_F32_WIDE:
-            launch_k(k_fused_batch<float, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk, S,
-                     passes, sync);
+            launch_k(k_fused_batch<float, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk,
+                     tickets, S, passes, sync);
             break;
         case TDS_F32:
-            launch_k(k_fused_batch<float, float, kSweep32>, g, dim3(kWG), 0, s, tm, D, tk, S,
-                     passes, sync);
+            launch_k(k_fused_batch<float, float, kSweep32>, g, dim3(kWG), 0, s, tm, D, tk,
+                     tickets, S, passes, sync);
             break;
         default:
             launch_k(k_fused_batch<float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D, tk,
-                     S, passes, sync);
+                     tickets, S, passes, sync);
             break;
     }
     return hipGetLastError();
