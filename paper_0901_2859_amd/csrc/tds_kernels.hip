@@ -1312,6 +1312,8 @@ constexpr int kSpinLimit = 1 << 22;
 // ticket increments, the tile counters' increments and the polls of waiting
 // workgroups do not contend for one cache line
 constexpr int kSyncStride = 64;   // ints (256 bytes)
+// work items per ticket of k_fused and k_fused_batch (their bodies take two)
+constexpr int32_t kFusedGroup = 2;
 
 struct FuseShape {
     int64_t T;           // tiles of W right-hand sides
@@ -1380,22 +1382,14 @@ constexpr int kFuseDenseBatch = 16;   // k-steps per operand load (register budg
 
 // sync: lines (kSyncStride ints) of [0] the ticket, [1] the error word,
 // [2, 2 + T) the beta counters, [2 + T, 2 + 2T) the interface counters;
-// zero before the launch
+// zero before the launch.
+// One work item of k_fused: item `rem` in ticket order.
 template <typename Fin, int KIND, bool DENSE, bool GEN>
-__global__ __launch_bounds__(2 * kHalfRhs, 4) void k_fused(
-    DevTables T, DevTables H, const Fin* __restrict__ F, double* __restrict__ X, int64_t N,
-    double* betaR, double* betaL, double* xsep, const double* __restrict__ Kt, int32_t Pc,
-    int32_t Mr, int32_t per, int32_t G, int32_t lgR, int passes, FuseShape fs, int* sync) {
-    static_assert(2 * kHalfRhs == kWG, "one workgroup shape for every item");
-    constexpr int LS = KIND == kSweepRefined ? kFuseSweepLds : kFuseSweep64Lds;
-    constexpr int L0 = LS > kFuseBetaLds ? LS : kFuseBetaLds;
-    constexpr int LDS = DENSE ? L0 : (L0 > kFuseScanLds ? L0 : kFuseScanLds);
-    __shared__ double smem[LDS];
-    __shared__ int64_t s_ticket;
-    if (threadIdx.x == 0)
-        s_ticket = __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    int64_t rem = s_ticket;
+__device__ __forceinline__ void fused_item(
+    const DevTables& T, const DevTables& H, const Fin* __restrict__ F, double* __restrict__ X,
+    int64_t N, double* betaR, double* betaL, double* xsep, const double* __restrict__ Kt,
+    int32_t Pc, int32_t Mr, int32_t per, int32_t G, int32_t lgR, int passes,
+    const FuseShape& fs, int* sync, int64_t rem, double* smem) {
     int* err = sync + kSyncStride;
     int* beta_done = sync + 2 * kSyncStride;                  // line 2 + tau
     int* iface_done = sync + (2 + fs.T) * kSyncStride;        // line 2 + T + tau
@@ -1464,6 +1458,35 @@ __global__ __launch_bounds__(2 * kHalfRhs, 4) void k_fused(
         beta_item_vec<64, Fin, true>(T, F, N, (int32_t)(idx / fs.bpt), bt, betaR, betaL,
                                      (double2*)smem);
         fuse_signal(beta_done + tau * kSyncStride);
+    }
+}
+
+// Workgroups increment the one ticket counter, and those increments are
+// serialised (some 12-14 ns each): a ticket takes kFusedGroup = 2
+// consecutive items, in order (a wait of the second is on earlier tickets
+// or on the first, already done).
+template <typename Fin, int KIND, bool DENSE, bool GEN>
+__global__ __launch_bounds__(2 * kHalfRhs, 4) void k_fused(
+    DevTables T, DevTables H, const Fin* __restrict__ F, double* __restrict__ X, int64_t N,
+    double* betaR, double* betaL, double* xsep, const double* __restrict__ Kt, int32_t Pc,
+    int32_t Mr, int32_t per, int32_t G, int32_t lgR, int passes, FuseShape fs, int* sync,
+    int64_t items) {
+    static_assert(2 * kHalfRhs == kWG, "one workgroup shape for every item");
+    constexpr int LS = KIND == kSweepRefined ? kFuseSweepLds : kFuseSweep64Lds;
+    constexpr int L0 = LS > kFuseBetaLds ? LS : kFuseBetaLds;
+    constexpr int LDS = DENSE ? L0 : (L0 > kFuseScanLds ? L0 : kFuseScanLds);
+    __shared__ double smem[LDS];
+    __shared__ int64_t s_ticket;
+    if (threadIdx.x == 0)
+        s_ticket = __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t q0 = s_ticket * kFusedGroup;
+    fused_item<Fin, KIND, DENSE, GEN>(T, H, F, X, N, betaR, betaL, xsep, Kt, Pc, Mr, per, G, lgR,
+                                      passes, fs, sync, q0, smem);
+    if (q0 + 1 < items) {
+        __syncthreads();                        // LDS of the first item
+        fused_item<Fin, KIND, DENSE, GEN>(T, H, F, X, N, betaR, betaL, xsep, Kt, Pc, Mr, per, G,
+                                          lgR, passes, fs, sync, q0 + 1, smem);
     }
 }
 
@@ -1586,9 +1609,6 @@ __global__ __launch_bounds__(2 * kWG, 4) void k_sweep_batch_halves(const BatchDe
 // whose blocks fit 32 rows.  sync: lines of kSyncStride ints: [0] the
 // ticket, [1] the error word, [2, 2 + S) the beta counters of the S tiles,
 // [2 + S, 2 + 2S) their interface counters; zero before the launch.
-// items per ticket of k_fused_batch (the kernel body takes two)
-constexpr int32_t kFusedGroup = 2;
-
 // one work item of k_fused_batch (code: its entry of the ticket table)
 template <typename Fin, typename Xout, int KIND>
 __device__ __forceinline__ void fused_batch_item(const BatchDesc* __restrict__ D, uint64_t code,
@@ -1888,9 +1908,10 @@ static hipError_t fused_t(const DevTables& t, const DevTables& h, const void* F,
                        sync, nsync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    launch_k(k_fused<Fin, KIND, DENSE, GEN>, dim3((unsigned)items), dim3(2 * kHalfRhs), 0, s, tm,
-             t, h, (const Fin*)F, (double*)X, N, betaR, betaL, xsep, Kt, Pc, Mr, per, G, lgR,
-             passes, fs, sync);
+    launch_k(k_fused<Fin, KIND, DENSE, GEN>,
+             dim3((unsigned)((items + kFusedGroup - 1) / kFusedGroup)), dim3(2 * kHalfRhs), 0, s,
+             tm, t, h, (const Fin*)F, (double*)X, N, betaR, betaL, xsep, Kt, Pc, Mr, per, G, lgR,
+             passes, fs, sync, items);
     return hipGetLastError();
 }
 
