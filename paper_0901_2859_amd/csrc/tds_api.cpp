@@ -879,21 +879,22 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     }
     if (items > 0x7fffffffLL || scans > 0x7fffffffLL) return TDS_EUNSUPPORTED;
     // the one-launch order (tdsolve_batch_set_fused) when every matrix with
-    // work is in the 32-row bucket: its tickets (per matrix the beta and the
-    // sweep items, and the interface items on 256-thread workgroups) and its
-    // counters behind the work slices
+    // work is in the 32-row bucket: its work items (per matrix the beta and
+    // the sweep items, and the interface items on 256-thread workgroups),
+    // written in order into the ticket table, and its counters behind the
+    // work slices
     const bool fused = h->fuse_lag > 0 && grp_items[1] == 0 && K < (1 << 30);
-    int64_t tickets = 0, ftiles = 0;
+    int64_t fitems = 0, ftiles = 0;
     size_t sync_off = 0;
     if (fused) {
         for (BatchDesc& d : desc) {
             d.tile0 = (int32_t)std::min<int64_t>(ftiles, INT32_MAX);
             if (d.N == 0) continue;
             ftiles += (d.N + kWG - 1) / kWG;
-            tickets += fused_items(d);
-            if (d.T.P > 1) tickets += fused_items(d) + fused_scans(d);
+            fitems += fused_items(d);
+            if (d.T.P > 1) fitems += fused_items(d) + fused_scans(d);
         }
-        if (tickets > 0x7fffffffLL || ftiles > 0x7fffffffLL) return TDS_EUNSUPPORTED;
+        if (fitems > 0x7fffffffLL || ftiles > 0x7fffffffLL) return TDS_EUNSUPPORTED;
         sync_off = align256(bytes);
         bytes = sync_off + align256(sizeof(int) * (size_t)fused_batch_sync_ints(ftiles));
     }
@@ -912,7 +913,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
     const size_t dbytes = align256(sizeof(BatchDesc) * desc.size());
     const size_t ibytes = align256(sizeof(int32_t) * (size_t)items);
     const size_t sbytes = align256(sizeof(int32_t) * (size_t)std::max<int64_t>(scans, 1));
-    const size_t total = dbytes + ibytes + sbytes + sizeof(uint64_t) * (size_t)tickets;
+    const size_t total = dbytes + ibytes + sbytes + sizeof(uint64_t) * (size_t)fitems;
     const int32_t lag = fused ? h->fuse_lag : 0;
     const bool same = desc.size() == h->desc.size() && lag == h->desc_lag &&
                       memcmp(desc.data(), h->desc.data(), sizeof(BatchDesc) * desc.size()) == 0;
@@ -971,7 +972,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
                 if (ss >= 0 && ss < S) blocks(kFusedSweep, ss);
                 if (st < S && desc[stage[st].first].T.P > 1) blocks(kFusedBeta, st);
             }
-            if (q != tickets) return TDS_EHIP;     // the counts above disagree
+            if (q != fitems) return TDS_EHIP;     // the counts above disagree
         }
         if (h->desc_bytes < total) {
             if (h->d_desc) {
@@ -1002,7 +1003,7 @@ int tdsolve_batch_series(tds_handle h, const void* const* F, void* const* X, con
         }
         const uint64_t* tk =
             (const uint64_t*)((const unsigned char*)h->d_desc + dbytes + ibytes + sbytes);
-        if (launch_fused_batch(h->d_desc, tk, tickets, ftiles, mode, h->passes,
+        if (launch_fused_batch(h->d_desc, tk, fitems, ftiles, mode, h->passes,
                                (int*)(general_of(h) + sync_off), (hipStream_t)stream,
                                tm ? tm + 2 : nullptr) != hipSuccess)
             return TDS_EHIP;

@@ -219,7 +219,7 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items,
 
 // The same three steps for all matrices of a batch in one launch (after a
 // small one that clears `sync`), every matrix in the 32-row bucket.  tk:
-// device array of `tickets` item codes in order, taken two per workgroup
+// device array of `nitems` item codes in order, taken two per workgroup
 // ticket (kind << 62 | matrix
 // << 32 | index of the item within its matrix; kinds kFusedBeta,
 // kFusedIface, kFusedSweep), the interface items on 256-thread workgroups
@@ -228,7 +228,7 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items,
 // device ints.  `tm` (may be null) times the launch.
 constexpr uint64_t kFusedBeta = 0, kFusedIface = 1, kFusedSweep = 2;
 int64_t fused_batch_sync_ints(int64_t S);
-hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t tickets,
+hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t nitems,
                               int64_t S, int mode, int passes, int* sync, hipStream_t s,
                               const KTime* tm);
 

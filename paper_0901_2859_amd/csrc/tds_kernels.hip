@@ -1295,11 +1295,13 @@ __global__ __launch_bounds__(kWG) void k_sweep_stream(DevTables T, const Fin* __
 // published their weights; a sweep item first solves its halves with zero
 // boundary values (the work that does not need the interface values) and
 // only then waits until the ni interface items of its tile have published
-// theirs.  Every wait is on items with smaller tickets: those have started
-// (running workgroups take tickets in increasing order) and never wait on a
-// larger ticket, so the item of the smallest unfinished ticket can always
-// progress and the launch cannot deadlock, however many workgroups are
-// resident.  Each wait is bounded all the same (kSpinLimit polls; past it
+// theirs.  The items are numbered in that order and a workgroup's ticket
+// names two consecutive ones, which it runs in turn.  Every wait is on an
+// earlier item: one of a smaller ticket, whose workgroup has started
+// (running workgroups take tickets in increasing order), or the same
+// workgroup's first item, already done; so the earliest unfinished item can
+// always progress and the launch cannot deadlock, however many workgroups
+// are resident.  Each wait is bounded all the same (kSpinLimit polls; past it
 // the error word is set and the item goes on).  Publishing: the values are
 // written through to the device's coherence point (st_w<true>), every wave
 // waits for its stores to complete, then one thread increments the tile's
@@ -1651,7 +1653,7 @@ __device__ __forceinline__ void fused_batch_item(const BatchDesc* __restrict__ D
 
 template <typename Fin, typename Xout, int KIND>
 __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, 32>())) void k_fused_batch(
-    const BatchDesc* __restrict__ D, const uint64_t* __restrict__ tk, int64_t tickets,
+    const BatchDesc* __restrict__ D, const uint64_t* __restrict__ tk, int64_t nitems,
     int64_t S, int passes, int* __restrict__ sync) {
     // LDS: the refined sweep's F (32 rows x 256 floats) or the interface scan
     constexpr int LSW = KIND == kSweepRefined ? 32 * kWG / 2 : 1;
@@ -1668,7 +1670,7 @@ __global__ __launch_bounds__(kWG, (sweep_min_waves<KIND, 32>())) void k_fused_ba
     // registers across the items and spill (3.66 and 3.71 ms).
     const int64_t q0 = (int64_t)__builtin_amdgcn_readfirstlane(s_ticket) * kFusedGroup;
     fused_batch_item<Fin, Xout, KIND>(D, cst(tk)[q0], S, passes, sync, smem);
-    if (q0 + 1 < tickets) {
+    if (q0 + 1 < nitems) {
         __syncthreads();                        // LDS of the first item
         fused_batch_item<Fin, Xout, KIND>(D, cst(tk)[q0 + 1], S, passes, sync, smem);
     }
@@ -2051,32 +2053,32 @@ hipError_t launch_batch(const BatchDesc* D, const int32_t* own_items, const int3
 int64_t fused_batch_sync_ints(int64_t S) { return kSyncStride * (2 + 2 * S); }
 
 
-hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t tickets, int64_t S,
+hipError_t launch_fused_batch(const BatchDesc* D, const uint64_t* tk, int64_t nitems, int64_t S,
                               int mode, int passes, int* sync, hipStream_t s, const KTime* tm) {
-    if (tickets == 0) return hipSuccess;
-    if (tickets > INT32_MAX || !sync || !tk) return hipErrorInvalidValue;
+    if (nitems == 0) return hipSuccess;
+    if (nitems > INT32_MAX || !sync || !tk) return hipErrorInvalidValue;
     const int64_t nsync = fused_batch_sync_ints(S);
     hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nsync + kWG - 1) / kWG)), dim3(kWG), 0, s,
                        sync, nsync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 g((unsigned)((tickets + kFusedGroup - 1) / kFusedGroup));
+    const dim3 g((unsigned)((nitems + kFusedGroup - 1) / kFusedGroup));
     switch (mode) {
         case TDS_F64:
             launch_k(k_fused_batch<double, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk,
-                     tickets, S, passes, sync);
+                     nitems, S, passes, sync);
             break;
         case TDS_F32_WIDE:
             launch_k(k_fused_batch<float, double, kSweep64>, g, dim3(kWG), 0, s, tm, D, tk,
-                     tickets, S, passes, sync);
+                     nitems, S, passes, sync);
             break;
         case TDS_F32:
             launch_k(k_fused_batch<float, float, kSweep32>, g, dim3(kWG), 0, s, tm, D, tk,
-                     tickets, S, passes, sync);
+                     nitems, S, passes, sync);
             break;
         default:
             launch_k(k_fused_batch<float, double, kSweepRefined>, g, dim3(kWG), 0, s, tm, D, tk,
-                     tickets, S, passes, sync);
+                     nitems, S, passes, sync);
             break;
     }
     return hipGetLastError();
