@@ -358,7 +358,8 @@ int tdsolve_batch_prepare(int32_t K, const double* const* a,
  * host arrays of K entries.  N: host array of K counts (0 allowed).  All K
  * series are solved by one launch of each kernel.  The per-matrix work
  * descriptors are uploaded only when pointers or counts differ from the
- * previous call, which synchronises `stream` (a host-to-device copy);
+ * previous call or the one-launch lag (tdsolve_batch_set_fused) changed,
+ * which synchronises `stream` (a host-to-device copy);
  * repeating a call with the same arguments issues kernel launches only, so
  * it can be captured in a HIP graph after one uncaptured call.
  * Errors: TDS_EINVAL (null arrays or pointers, N[k] < 0, F[k] == X[k] with

@@ -29,8 +29,8 @@ struct tds_plan {
     int32_t iface = TDS_IFACE_RECURRENCE;   // interface-step evaluation order
     double* dense_K = nullptr;   // Theorem 2 coefficient table (TDS_IFACE_DENSE)
     int32_t dense_Pc = 0, dense_Mr = 0;
-    int32_t fuse_lag = 0;        // fused order: sweeps this many tiles (batch: matrices)
-                                 //   behind (0: three kernels)
+    int32_t fuse_lag = 0;        // fused order: interface items this many tiles behind the
+                                 //   weights, sweeps twice that (0: separate kernels)
     int32_t fuse_cols = 0;       // fused order: right-hand sides per tile
     int device = 0;
     void* work = nullptr;        // grows with N
