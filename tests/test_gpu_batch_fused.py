@@ -148,3 +148,29 @@ def test_fused_batch_lag_limits():
             bp.set_fused(lag)
     bp.set_fused(64)
     bp.set_fused(0)
+
+
+def test_fused_batch_status_and_phase_timing():
+    # the last one-launch solve is what tdsolve_status checks, and phase
+    # timing reports the one launch as the sweep phase
+    w = wl.uneven_batch(seed=6, K=10, M_lo=128, M_hi=2000, N_hi=500)
+    items = w["items"]
+    bp = t.BatchPlan([it["a"] for it in items], [it["b"] for it in items],
+                     [_rows32(it["M"]) for it in items])
+    bp.set_refinement(2)
+    Fs = _inputs(items, "f32_refined")
+    bp.set_fused(0)
+    bp.solve(Fs, mode="f32_refined")
+    eta0, passes0 = bp.status()
+    bp.set_fused(4)
+    Xs = bp.solve(Fs, mode="f32_refined")
+    eta1, passes1 = bp.status()
+    assert eta1 == eta0 and passes1 == passes0 == 2
+    assert 0.0 < eta1 < 1e-14
+    bp.timing(True)
+    bp.timing_read()
+    for _ in range(3):
+        bp.solve(Fs, Xs, mode="f32_refined")
+    mb, mi, ms, calls = bp.timing_read()
+    bp.timing(False)
+    assert calls == 3 and mb == 0.0 and mi == 0.0 and ms > 0.0
